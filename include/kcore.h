@@ -1,0 +1,124 @@
+/*
+ * kcore.h -- C ABI of libkcore, exact k-core decomposition on MI355X (gfx950).
+ *
+ * Method (paper: Sec. II-B, Alg. 1 -- the Montresor et al. protocol -- and its
+ * shared-memory form FastK, Sec. IV, Alg. 4): every vertex starts with its
+ * degree as coreness estimate and repeatedly lowers it to the h-index of its
+ * neighbours' estimates, capped by its own value, until no estimate changes.
+ * Estimates never increase (Sec. III, selective message sending) and the fixed
+ * point reached from the degrees is exactly the coreness of Definition 1
+ * (Sec. II): the largest k whose k-core (maximal vertex set inducing minimum
+ * degree >= k) contains the vertex; 0 for isolated vertices.
+ *
+ * Graph input everywhere: an undirected graph as a symmetric CSR.
+ *   row_ptr[n+1]  offsets into col_idx, row_ptr[0] == 0, non-decreasing;
+ *   col_idx[nnz]  neighbour ids in [0, n), int32; every edge {u,v} appears as
+ *                 v in row u AND u in row v; no self-loops; no duplicate entries
+ *                 (the paper removes self-loops and treats graphs as undirected,
+ *                 Sec. V-A).  Rows sorted ascending are recommended (locality),
+ *                 not required.
+ * Preconditions are checked only when the environment variable
+ * KCORE_VALIDATE=1 is set (then a violation returns KCORE_E_INVALID); otherwise
+ * violating them gives unspecified (but memory-safe for in-range ids) results.
+ *
+ * Output: out_core[n] int32, the coreness of every vertex, bit-exact.
+ *
+ * Errors: every call returns a kcore_status; no C++ exception crosses the ABI.
+ * kcore_last_error() returns a thread-local description of the last failure.
+ */
+#ifndef KCORE_H_
+#define KCORE_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KCORE_OK = 0,
+  KCORE_E_INVALID = -1,   /* bad argument or (with KCORE_VALIDATE=1) bad CSR */
+  KCORE_E_NOMEM = -2,     /* device or host allocation failed */
+  KCORE_E_HIP = -3,       /* a HIP runtime call failed */
+  KCORE_E_TOO_LARGE = -4, /* request larger than the configured memory budget */
+  KCORE_E_AGAIN = -5,     /* queue full, retry later */
+  KCORE_E_CANCELLED = -6, /* request cancelled (server destroyed) */
+  KCORE_E_TIMEOUT = -7    /* wait timed out */
+} kcore_status;
+
+/* Tuning knobs of the round kernels.  Zero in a field means "library default".
+ * Results never depend on these values; only speed does. */
+typedef struct kcore_tuning {
+  int32_t thread_max_deg;  /* vertices with degree <= this: one lane each (max 8) */
+  int32_t wave_max_deg;    /* <= this: one 64-lane wavefront each (max 1024); above: one workgroup */
+  int32_t block_max_deg;   /* <= this: workgroup keeps values in registers; above: multi-pass search */
+  int32_t tail_threshold;  /* frontier size at or below which one workgroup finishes the run (<0: never) */
+  int32_t grid_blocks;     /* workgroups per round launch (0: 8 per compute unit) */
+  int32_t rounds_per_poll; /* rounds enqueued between host checks of the frontier (first chunk) */
+  int32_t activation;      /* 0: guarded two-sided rule (default), 1: one-sided rule */
+  int32_t timing;          /* 1: bracket every round launch with HIP events (fills the *_ms statistics) */
+  int32_t reserved[8];
+} kcore_tuning;
+
+/* Per-call statistics (optional output).  Edge visits count the adjacency
+ * entries scanned by the h-index update. */
+typedef struct kcore_stats {
+  int64_t rounds;          /* rounds until the frontier emptied (multi-workgroup + tail) */
+  int64_t tail_rounds;     /* of which run inside the single-workgroup tail */
+  int64_t launches;        /* round-kernel launches */
+  int64_t vertex_updates;  /* vertices whose h-index was recomputed */
+  int64_t edge_visits;     /* adjacency entries read by those recomputations */
+  int64_t changes;         /* estimate decreases */
+  int64_t activations;     /* vertices appended to a next frontier */
+  /* first (dense) round alone; filled only when tuning.timing == 1 */
+  int64_t dense_vertex_updates;
+  int64_t dense_edge_visits;
+  int64_t dense_changes;
+  int64_t dense_activations;
+  double dense_ms;         /* duration of the dense round kernel (timing mode) */
+  double sparse_ms;        /* summed durations of all later round kernels (timing mode) */
+  int64_t reserved[3];
+} kcore_stats;
+
+/*
+ * kcore_decompose -- coreness of one graph with int64 row offsets.
+ *   n         number of vertices, 0 <= n <= 2^31-1 (ids are int32); n == 0 is a no-op.
+ *   row_ptr   DEVICE pointer, int64[n+1].
+ *   col_idx   DEVICE pointer, int32[row_ptr[n]].
+ *   out_core  DEVICE pointer, int32[n]; written with the coreness.  Must not
+ *             alias row_ptr or col_idx.  Used as the estimate array during the run.
+ *   stream    hipStream_t (as void*), NULL for the default stream.
+ * All graph buffers are owned by the caller and only read.  The library keeps
+ * a per-device workspace (about 9 bytes per vertex plus a small control block),
+ * allocated on first use, grown on demand and reused by later calls.
+ * Work is enqueued on `stream`; the call returns after the fixpoint has been
+ * reached (it synchronises `stream` a few times to test for convergence), so
+ * out_core is final on return.  Calls from several host threads are
+ * serialised per device.
+ */
+kcore_status kcore_decompose(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
+                             void* stream);
+
+/* Same with int32 row offsets (graphs with fewer than 2^31 adjacency entries). */
+kcore_status kcore_decompose32(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
+                               void* stream);
+
+/* kcore_decompose with explicit tuning (NULL = defaults) and optional statistics (NULL = none). */
+kcore_status kcore_decompose_ex(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
+                                const kcore_tuning* tuning, kcore_stats* stats, void* stream);
+
+/* Thread-local message for the last non-OK status returned on this thread. */
+const char* kcore_last_error(void);
+
+/* Library version string. */
+const char* kcore_version(void);
+
+/* Release the workspace held for the current device (optional; it is also
+ * released at process exit). */
+kcore_status kcore_release_workspace(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KCORE_H_ */

@@ -1,0 +1,157 @@
+"""Exact k-core decomposition on MI355X (gfx950) -- Python binding of libkcore.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libkcore.so`` (built in-tree by ``build.py``).  PyTorch supplies
+device memory and the stream.  There is no CPU fallback: if the library is
+missing or no GPU is present, the calls raise.
+
+The method is the iterative coreness computation of the paper (Sec. II-B,
+Alg. 1; FastK, Sec. IV): estimates start at the degree and are lowered to the
+h-index of the neighbours' estimates until nothing changes; the fixed point is
+the coreness of Definition 1 (Sec. II), bit-exact.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["decompose", "Tuning", "Stats", "KcoreError", "library_path", "load", "version"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libkcore.so")
+_lib = None
+
+STATUS = {
+    0: "KCORE_OK", -1: "KCORE_E_INVALID", -2: "KCORE_E_NOMEM", -3: "KCORE_E_HIP", -4: "KCORE_E_TOO_LARGE",
+    -5: "KCORE_E_AGAIN", -6: "KCORE_E_CANCELLED", -7: "KCORE_E_TIMEOUT",
+}
+
+
+class KcoreError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Tuning(ctypes.Structure):
+    """Mirror of ``kcore_tuning`` (zero = library default)."""
+    _fields_ = [
+        ("thread_max_deg", ctypes.c_int32),
+        ("wave_max_deg", ctypes.c_int32),
+        ("block_max_deg", ctypes.c_int32),
+        ("tail_threshold", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
+        ("rounds_per_poll", ctypes.c_int32),
+        ("activation", ctypes.c_int32),
+        ("timing", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 8),
+    ]
+
+
+class Stats(ctypes.Structure):
+    """Mirror of ``kcore_stats``."""
+    _fields_ = [
+        ("rounds", ctypes.c_int64),
+        ("tail_rounds", ctypes.c_int64),
+        ("launches", ctypes.c_int64),
+        ("vertex_updates", ctypes.c_int64),
+        ("edge_visits", ctypes.c_int64),
+        ("changes", ctypes.c_int64),
+        ("activations", ctypes.c_int64),
+        ("dense_vertex_updates", ctypes.c_int64),
+        ("dense_edge_visits", ctypes.c_int64),
+        ("dense_changes", ctypes.c_int64),
+        ("dense_activations", ctypes.c_int64),
+        ("dense_ms", ctypes.c_double),
+        ("sparse_ms", ctypes.c_double),
+        ("reserved", ctypes.c_int64 * 3),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: (getattr(self, name) if name != "reserved" else None) for name, _ in self._fields_
+                if name != "reserved"}
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libkcore.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"libkcore.so not built at {_LIB_PATH}; run python -m paper_2512_00233_amd.build")
+    lib = ctypes.CDLL(_LIB_PATH)
+    i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+    lib.kcore_decompose.restype = i32
+    lib.kcore_decompose.argtypes = [i64, vp, vp, vp, vp]
+    lib.kcore_decompose32.restype = i32
+    lib.kcore_decompose32.argtypes = [i64, vp, vp, vp, vp]
+    lib.kcore_decompose_ex.restype = i32
+    lib.kcore_decompose_ex.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats), vp]
+    lib.kcore_last_error.restype = ctypes.c_char_p
+    lib.kcore_last_error.argtypes = []
+    lib.kcore_version.restype = ctypes.c_char_p
+    lib.kcore_version.argtypes = []
+    lib.kcore_release_workspace.restype = i32
+    lib.kcore_release_workspace.argtypes = []
+    _lib = lib
+    return lib
+
+
+def version() -> str:
+    return load().kcore_version().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise KcoreError(status, load().kcore_last_error().decode())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def decompose(row_ptr, col_idx, out=None, tuning: Tuning | None = None, stats: Stats | None = None,
+              stream=None):
+    """Coreness of every vertex of an undirected graph given as a symmetric CSR.
+
+    row_ptr: int64 (or int32) CUDA tensor [n+1]; col_idx: int32 CUDA tensor [nnz].
+    Returns ``out`` (int32 CUDA tensor [n], allocated when None).  The call
+    returns once the result is final.  ``stats``, if given, is filled in.
+    """
+    import torch
+    lib = load()
+    if not (row_ptr.is_cuda and col_idx.is_cuda):
+        raise ValueError("row_ptr and col_idx must be CUDA tensors")
+    if col_idx.dtype != torch.int32:
+        raise TypeError("col_idx must be int32")
+    if row_ptr.dtype not in (torch.int64, torch.int32):
+        raise TypeError("row_ptr must be int64 or int32")
+    if not (row_ptr.is_contiguous() and col_idx.is_contiguous()):
+        raise ValueError("row_ptr and col_idx must be contiguous")
+    n = row_ptr.numel() - 1
+    if n < 0:
+        raise ValueError("row_ptr must have at least one element")
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+    elif out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError("out must be a contiguous int32 CUDA tensor of n elements")
+    col_ptr = col_idx.data_ptr() if col_idx.numel() else out.data_ptr()  # any valid pointer when nnz == 0
+    st = _stream_handle(stream)
+    if row_ptr.dtype == torch.int32:
+        if tuning is not None or stats is not None:
+            raise ValueError("tuning/stats are available with int64 row_ptr only")
+        _check(lib.kcore_decompose32(n, row_ptr.data_ptr(), col_ptr, out.data_ptr(), st))
+    elif tuning is None and stats is None:
+        _check(lib.kcore_decompose(n, row_ptr.data_ptr(), col_ptr, out.data_ptr(), st))
+    else:
+        _check(lib.kcore_decompose_ex(n, row_ptr.data_ptr(), col_ptr, out.data_ptr(),
+                                      ctypes.byref(tuning) if tuning is not None else None,
+                                      ctypes.byref(stats) if stats is not None else None, st))
+    return out

@@ -1,0 +1,311 @@
+// Host runtime and C ABI of libkcore: workspace per device, the round driver
+// (dense first round, sparse rounds enqueued in chunks, convergence polled on a
+// pinned copy of the device control block) and argument checking.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/kcore.h"
+#include "kcore_kernels_impl.h"
+#include "kcore_runtime.h"
+
+namespace kcore {
+
+static thread_local std::string g_last_error;
+
+kcore_status fail(kcore_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+kcore_status hip_fail(hipError_t e, const char* what) {
+  return fail(KCORE_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define KC_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+// ------------------------------------------------------------------ workspace
+struct Workspace {
+  int device = -1;
+  int num_cus = 0;
+  int64_t cap_n = 0;
+  int32_t* stamp = nullptr;
+  uint8_t* cls = nullptr;
+  int32_t* lists[2] = {nullptr, nullptr};
+  Ctl* ctl = nullptr;
+  Ctl* host_ctl = nullptr;   // pinned
+  int32_t* verr = nullptr;   // validation result (device)
+  int32_t* host_verr = nullptr;
+  int32_t epoch = 1;
+  std::vector<hipEvent_t> events;  // timing mode: one pair per round launch
+  std::mutex mu;
+
+  kcore_status need_events(size_t count) {
+    while (events.size() < count) {
+      hipEvent_t e;
+      KC_HIP(hipEventCreate(&e));
+      events.push_back(e);
+    }
+    return KCORE_OK;
+  }
+
+  void release() {
+    (void)hipFree(stamp);
+    (void)hipFree(cls);
+    (void)hipFree(lists[0]);
+    (void)hipFree(lists[1]);
+    stamp = nullptr;
+    cls = nullptr;
+    lists[0] = lists[1] = nullptr;
+    cap_n = 0;
+  }
+};
+
+static std::mutex g_ws_mu;
+static Workspace* g_ws[64];
+
+static kcore_status get_workspace(Workspace** out) {
+  int dev = 0;
+  KC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(KCORE_E_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if (!g_ws[dev]) {
+    auto* ws = new Workspace();
+    ws->device = dev;
+    hipDeviceProp_t prop;
+    KC_HIP(hipGetDeviceProperties(&prop, dev));
+    ws->num_cus = prop.multiProcessorCount;
+    KC_HIP(hipMalloc(&ws->ctl, sizeof(Ctl)));
+    KC_HIP(hipHostMalloc(&ws->host_ctl, sizeof(Ctl), hipHostMallocDefault));
+    KC_HIP(hipMalloc(&ws->verr, sizeof(int32_t)));
+    KC_HIP(hipHostMalloc(&ws->host_verr, sizeof(int32_t), hipHostMallocDefault));
+    g_ws[dev] = ws;
+  }
+  *out = g_ws[dev];
+  return KCORE_OK;
+}
+
+static kcore_status ensure_capacity(Workspace* ws, int64_t n, hipStream_t st) {
+  if (n <= ws->cap_n) return KCORE_OK;
+  KC_HIP(hipStreamSynchronize(st));
+  ws->release();
+  int64_t cap = std::max<int64_t>(n, 1024);
+  if (hipMalloc(&ws->stamp, sizeof(int32_t) * cap) != hipSuccess ||
+      hipMalloc(&ws->cls, sizeof(uint8_t) * cap) != hipSuccess ||
+      hipMalloc(&ws->lists[0], sizeof(int32_t) * cap) != hipSuccess ||
+      hipMalloc(&ws->lists[1], sizeof(int32_t) * cap) != hipSuccess) {
+    (void)hipGetLastError();
+    ws->release();
+    return fail(KCORE_E_NOMEM, "workspace allocation failed for n=" + std::to_string(n));
+  }
+  KC_HIP(hipMemsetAsync(ws->stamp, 0, sizeof(int32_t) * cap, st));
+  ws->cap_n = cap;
+  ws->epoch = 1;
+  return KCORE_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
+  Tuning r;
+  r.t1 = kThreadMaxDeg;
+  r.t2 = kWave * kWaveRegs;
+  r.t3 = 256 * kBlockRegs;
+  r.tail = 2048;
+  r.grid = 8 * num_cus;
+  r.poll = 4;
+  r.one_sided = 0;
+  r.timing = 0;
+  if (const char* e = std::getenv("KCORE_TAIL")) r.tail = std::atoi(e);
+  if (t) {
+    if (t->thread_max_deg > 0) r.t1 = std::min(t->thread_max_deg, kThreadMaxDeg);
+    if (t->wave_max_deg > 0) r.t2 = std::min(t->wave_max_deg, kWave * kWaveRegs);
+    if (t->block_max_deg > 0) r.t3 = std::min(t->block_max_deg, 256 * kBlockRegs);
+    if (t->tail_threshold > 0) r.tail = t->tail_threshold;
+    else if (t->tail_threshold < 0) r.tail = 0;  // tail disabled
+    if (t->grid_blocks > 0) r.grid = t->grid_blocks;
+    if (t->rounds_per_poll > 0) r.poll = t->rounds_per_poll;
+    r.one_sided = t->activation == 1;
+    r.timing = t->timing == 1;
+  }
+  r.t1 = std::max(r.t1, 1);
+  r.t2 = std::max(r.t2, r.t1);
+  r.grid = std::max(8, (r.grid + 7) / 8 * 8);
+  return r;
+}
+
+static bool env_validate() {
+  const char* e = std::getenv("KCORE_VALIDATE");
+  return e && e[0] == '1';
+}
+
+// ------------------------------------------------------------------ driver
+constexpr int kBlock = 256;
+
+template <typename Off>
+static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t* col, int32_t* out,
+                                   const kcore_tuning* tuning, kcore_stats* stats, hipStream_t st) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (n < 0 || n > INT32_MAX) return fail(KCORE_E_INVALID, "n must be in [0, 2^31-1]");
+  if (n == 0) return KCORE_OK;
+  if (!row_ptr || !col || !out) return fail(KCORE_E_INVALID, "null pointer argument");
+  Workspace* ws = nullptr;
+  kcore_status s = get_workspace(&ws);
+  if (s != KCORE_OK) return s;
+  std::lock_guard<std::mutex> lk(ws->mu);
+  s = ensure_capacity(ws, n, st);
+  if (s != KCORE_OK) return s;
+  const Tuning tu = resolve_tuning(tuning, ws->num_cus);
+  const int init_grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
+
+  if (env_validate()) {
+    KC_HIP(hipMemsetAsync(ws->verr, 0x7f, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_validate<Off>, dim3(init_grid), dim3(kBlock), 0, st, n, row_ptr, col, ws->verr);
+    KC_HIP(hipGetLastError());
+    KC_HIP(hipMemcpyAsync(ws->host_verr, ws->verr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    KC_HIP(hipStreamSynchronize(st));
+    int32_t code = *ws->host_verr;
+    if (code != 0x7f7f7f7f) {
+      static const char* what[] = {"", "neighbour id out of range", "self-loop", "row not strictly increasing",
+                                   "graph not symmetric"};
+      return fail(KCORE_E_INVALID, std::string("KCORE_VALIDATE: ") + what[std::min(code, 4)]);
+    }
+  }
+
+  if (ws->epoch > (1 << 29)) {
+    KC_HIP(hipMemsetAsync(ws->stamp, 0, sizeof(int32_t) * ws->cap_n, st));
+    ws->epoch = 1;
+  }
+  Args<Off> a;
+  a.n = n;
+  a.row_ptr = row_ptr;
+  a.col = col;
+  a.est = out;
+  a.stamp = ws->stamp;
+  a.cls = ws->cls;
+  a.lists[0] = ws->lists[0];
+  a.lists[1] = ws->lists[1];
+  a.ctl = ws->ctl;
+  a.t1 = tu.t1;
+  a.t2 = tu.t2;
+  a.t3 = tu.t3;
+  a.tail_threshold = tu.tail;
+  a.one_sided = tu.one_sided;
+
+  const int32_t r0 = ws->epoch;
+  double dense_ms = 0, sparse_ms = 0;
+  unsigned long long dense_st[4] = {0, 0, 0, 0};
+  if (tu.timing) {
+    s = ws->need_events(2 * 64);
+    if (s != KCORE_OK) return s;
+  }
+  KC_HIP(hipMemsetAsync(ws->ctl, 0, sizeof(Ctl), st));
+  hipLaunchKernelGGL(k_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL(k_seed<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, r0);
+  if (tu.timing) KC_HIP(hipEventRecord(ws->events[0], st));
+  hipLaunchKernelGGL((k_round<kBlock, true, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, r0);
+  KC_HIP(hipGetLastError());
+  if (tu.timing) {
+    KC_HIP(hipEventRecord(ws->events[1], st));
+    KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    KC_HIP(hipStreamSynchronize(st));
+    float ms = 0;
+    KC_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
+    dense_ms = ms;
+    for (int q = 0; q < 4; ++q) dense_st[q] = ws->host_ctl->stats[ST_UPDATES + q];
+  }
+  int64_t launches = 1;
+  int32_t r = r0 + 1;
+  int K = tu.poll;
+  for (;;) {
+    for (int i = 0; i < K; ++i) {
+      if (tu.timing) KC_HIP(hipEventRecord(ws->events[2 * i], st));
+      hipLaunchKernelGGL((k_round<kBlock, false, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, r + i);
+      if (tu.timing) KC_HIP(hipEventRecord(ws->events[2 * i + 1], st));
+    }
+    KC_HIP(hipGetLastError());
+    launches += K;
+    r += K;
+    KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    KC_HIP(hipStreamSynchronize(st));
+    if (tu.timing) {
+      for (int i = 0; i < K; ++i) {
+        float ms = 0;
+        KC_HIP(hipEventElapsedTime(&ms, ws->events[2 * i], ws->events[2 * i + 1]));
+        sparse_ms += ms;
+      }
+    }
+    const int32_t* c = ws->host_ctl->cnt[r % 3];
+    if (c[0] == 0 && c[1] == 0 && c[2] == 0) break;
+    if ((int64_t)r - r0 > (int64_t)1 << 24) return fail(KCORE_E_HIP, "round limit exceeded");
+    K = std::min(2 * K, 64);
+  }
+  const Ctl& hc = *ws->host_ctl;
+  if (hc.error) return fail(KCORE_E_HIP, "tail round cap reached (internal error)");
+  ws->epoch = r + (int32_t)hc.stats[ST_TAIL_ROUNDS] + 4;
+  if (stats) {
+    stats->rounds = (int64_t)hc.stats[ST_ROUNDS];
+    stats->tail_rounds = (int64_t)hc.stats[ST_TAIL_ROUNDS];
+    stats->launches = launches;
+    stats->vertex_updates = (int64_t)hc.stats[ST_UPDATES];
+    stats->edge_visits = (int64_t)hc.stats[ST_VISITS];
+    stats->changes = (int64_t)hc.stats[ST_CHANGES];
+    stats->activations = (int64_t)hc.stats[ST_ACTIVATIONS];
+    stats->dense_vertex_updates = (int64_t)dense_st[0];
+    stats->dense_edge_visits = (int64_t)dense_st[1];
+    stats->dense_changes = (int64_t)dense_st[2];
+    stats->dense_activations = (int64_t)dense_st[3];
+    stats->dense_ms = dense_ms;
+    stats->sparse_ms = sparse_ms;
+  }
+  return KCORE_OK;
+}
+
+}  // namespace kcore
+
+using namespace kcore;
+
+extern "C" {
+
+kcore_status kcore_decompose(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
+                             void* stream) {
+  return decompose_impl<int64_t>(n, row_ptr, col_idx, out_core, nullptr, nullptr, (hipStream_t)stream);
+}
+
+kcore_status kcore_decompose32(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
+                               void* stream) {
+  return decompose_impl<int32_t>(n, row_ptr, col_idx, out_core, nullptr, nullptr, (hipStream_t)stream);
+}
+
+kcore_status kcore_decompose_ex(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
+                                const kcore_tuning* tuning, kcore_stats* stats, void* stream) {
+  return decompose_impl<int64_t>(n, row_ptr, col_idx, out_core, tuning, stats, (hipStream_t)stream);
+}
+
+const char* kcore_last_error(void) { return g_last_error.c_str(); }
+
+const char* kcore_version(void) { return "kcore-mi355x 0.1.0 (gfx950)"; }
+
+kcore_status kcore_release_workspace(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(KCORE_E_HIP, "no device");
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  Workspace* ws = g_ws[dev];
+  if (ws) {
+    std::lock_guard<std::mutex> lk2(ws->mu);
+    (void)hipDeviceSynchronize();
+    ws->release();
+  }
+  return KCORE_OK;
+}
+
+}  // extern "C"

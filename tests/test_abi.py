@@ -1,0 +1,52 @@
+"""The C-ABI library loads and exports every function include/kcore.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(kcore_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["kcore_decompose", "kcore_decompose32", "kcore_last_error"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2512_00233_amd as kc
+    if not os.path.exists(kc.library_path()):
+        pytest.skip("libkcore.so not built")
+    lib = ctypes.CDLL(kc.library_path())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_error_without_gpu():
+    import paper_2512_00233_amd as kc
+    if not os.path.exists(kc.library_path()):
+        pytest.skip("libkcore.so not built")
+    assert "gfx950" in kc.version()
+    lib = kc.load()
+    # argument checks run before any device call
+    assert lib.kcore_decompose(-5, None, None, None, None) == -1
+    assert b"n must be" in lib.kcore_last_error()
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    import paper_2512_00233_amd as kc
+    monkeypatch.setattr(kc, "_lib", None)
+    monkeypatch.setattr(kc, "_LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        kc.load()

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit-exact.
+
+Coreness is integer, so the bar is equality on every vertex (tolerance 0).
+Every GPU result is also run through the oracle's local certificate.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from tests import small_graphs as sg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def kc():
+    import paper_2512_00233_amd as kc
+    return kc
+
+
+def run_gpu(row_ptr, col_idx, int32_rows=False, tuning=None, stats=None):
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(np.ascontiguousarray(row_ptr, dtype=np.int32 if int32_rows else np.int64)).to(dev)
+    ci = torch.from_numpy(np.ascontiguousarray(col_idx, dtype=np.int32)).to(dev)
+    out = kc().decompose(rp, ci, tuning=tuning, stats=stats)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def assert_parity(name, row_ptr, col_idx, **kw):
+    print(f"[parity] {name}: n={len(row_ptr) - 1} nnz={len(col_idx)} {kw}", flush=True)
+    got = run_gpu(row_ptr, col_idx, **kw)
+    ref = oracle.coreness(row_ptr, col_idx)
+    if not np.array_equal(got, ref):
+        bad = np.nonzero(got != ref)[0]
+        raise AssertionError(f"{name}: {bad.size} mismatches, first v={bad[0]} gpu={got[bad[0]]} ref={ref[bad[0]]}")
+    assert oracle.check(row_ptr, col_idx, got)[0] == 0
+    return got
+
+
+# ---------------------------------------------------------------- small fixtures
+def test_golden_small_graphs():
+    from tests.golden.load import small_graphs
+    for name, n, edges, core in small_graphs():
+        rp, ci = sg.to_csr(n, edges)
+        got = run_gpu(rp, ci)
+        assert got.tolist() == core, name
+
+
+def test_closed_forms():
+    cases = [
+        ("K40", sg.complete(40), 39),
+        ("C1000", sg.cycle(1000), 2),
+        ("grid64x80", sg.grid(64, 80), 2),
+        ("Q8", sg.hypercube(8), 8),
+        ("K30,50", sg.complete_bipartite(30, 50), 30),
+        ("petersen", sg.petersen(), 3),
+        ("wheel50", sg.wheel(50), 3),
+    ]
+    for name, (n, edges), k in cases:
+        rp, ci = sg.to_csr(n, edges)
+        assert run_gpu(rp, ci).tolist() == [k] * n, name
+
+
+# ---------------------------------------------------------------- edge cases
+def test_empty_and_degenerate():
+    assert run_gpu(np.zeros(1, np.int64), np.zeros(0, np.int32)).size == 0          # n = 0
+    assert run_gpu(np.zeros(2, np.int64), np.zeros(0, np.int32)).tolist() == [0]   # n = 1
+    assert run_gpu(np.zeros(1001, np.int64), np.zeros(0, np.int32)).tolist() == [0] * 1000  # no edges
+    rp, ci = sg.to_csr(2, [(0, 1)])
+    assert run_gpu(rp, ci).tolist() == [1, 1]
+
+
+def test_star_with_a_million_leaves():
+    n, edges = sg.star(1_000_000)
+    g = gg.from_edges(n, [e[0] for e in edges], [e[1] for e in edges])
+    got = run_gpu(g.row_ptr, g.col_idx)
+    assert (got == 1).all()
+
+
+@pytest.mark.parametrize("k", [200, 1500, 3000])
+def test_large_cliques(k):
+    # wavefront path (k-1 <= 512), workgroup register path (<= 2048), multi-pass path (> 2048)
+    n, edges = sg.complete(k)
+    rp, ci = sg.to_csr(n, edges)
+    assert (run_gpu(rp, ci) == k - 1).all()
+
+
+def test_long_path_and_onion():
+    n = 200_000
+    g = gg.from_edges(n, np.arange(n - 1), np.arange(1, n))
+    assert (run_gpu(g.row_ptr, g.col_idx) == 1).all()
+    sizes = [3, 50, 7, 600, 9, 2200, 4]
+    n, edges = sg.onion(sizes)
+    rp, ci = sg.to_csr(n, edges)
+    assert_parity("onion", rp, ci)
+
+
+def test_hubs_over_a_core():
+    # a dense core (ER) plus hubs with tens of thousands of pendant leaves
+    rng = np.random.default_rng(7)
+    core_n, leaves = 3000, 60000
+    src = list(rng.integers(0, core_n, 40000))
+    dst = list(rng.integers(0, core_n, 40000))
+    for h in range(5):
+        src += [h] * (leaves // 5)
+        dst += list(range(core_n + h * (leaves // 5), core_n + (h + 1) * (leaves // 5)))
+    g = gg.from_edges(core_n + leaves, src, dst)
+    assert_parity("hubs", g.row_ptr, g.col_idx)
+
+
+# ---------------------------------------------------------------- workloads
+def test_er_small_int32_and_int64_rows():
+    g = gg.workload("er_small")
+    a = assert_parity("er_small/int64", g.row_ptr, g.col_idx)
+    b = run_gpu(g.row_ptr, g.col_idx, int32_rows=True)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name", ["road_512", "rmat16", "rmat20"])
+def test_medium_workloads(name):
+    g = gg.workload(name)
+    assert_parity(name, g.row_ptr, g.col_idx)
+
+
+def test_chung_lu_and_batch_members():
+    for gamma in (2.1, 2.5):
+        g = gg.chung_lu(200_000, gamma, 16, seed=11)
+        assert_parity(f"chung_lu{gamma}", g.row_ptr, g.col_idx)
+    b = gg.batch(6, seed=4, nmin=1000, nmax=100_000)
+    for i in range(b.num_graphs):
+        sub = b.graph(i)
+        assert_parity(f"batch[{i}]", sub.row_ptr, sub.col_idx)
+
+
+@pytest.mark.parametrize("name", ["road", "rmat24"])
+def test_full_size_workloads(name):
+    g = gg.workload(name)
+    kc_ = kc()
+    st = kc_.Stats()
+    got = run_gpu(g.row_ptr, g.col_idx, stats=st)
+    ref = oracle.coreness(g.row_ptr, g.col_idx)
+    print(f"[parity] {name}: rounds={st.rounds} tail={st.tail_rounds} visits={st.edge_visits}", flush=True)
+    assert np.array_equal(got, ref)
+    assert oracle.check(g.row_ptr, g.col_idx, got)[0] == 0
+
+
+# ---------------------------------------------------------------- schedule independence
+TUNINGS = {
+    "defaults": {},
+    "no_tail": dict(tail_threshold=-1),
+    "tail_everything": dict(tail_threshold=1 << 30),
+    "one_sided": dict(activation=1),
+    "tiny_grid": dict(grid_blocks=8),
+    "lane_only_small": dict(thread_max_deg=2, wave_max_deg=64, block_max_deg=256),
+    "all_huge": dict(thread_max_deg=1, wave_max_deg=1, block_max_deg=1),
+    "poll_every_round": dict(rounds_per_poll=1, timing=1),
+}
+
+
+@pytest.mark.parametrize("tname", list(TUNINGS))
+def test_results_do_not_depend_on_tuning(tname):
+    kc_ = kc()
+    t = kc_.Tuning(**TUNINGS[tname])
+    for name in ["rmat16", "road_512"]:
+        g = gg.workload(name)
+        st = kc_.Stats()
+        got = run_gpu(g.row_ptr, g.col_idx, tuning=t, stats=st)
+        assert np.array_equal(got, oracle.coreness(g.row_ptr, g.col_idx)), (tname, name)
+        assert st.rounds >= 1
+
+
+def test_workspace_reuse_across_sizes():
+    seq = ["rmat16", "er_small", "road_512", "rmat16", "er_small"]
+    for name in seq:
+        g = gg.workload(name)
+        assert_parity(f"reuse/{name}", g.row_ptr, g.col_idx)
+
+
+# ---------------------------------------------------------------- errors
+def test_invalid_arguments_raise():
+    kc_ = kc()
+    lib = kc_.load()
+    assert lib.kcore_decompose(-1, None, None, None, None) == -1
+    assert lib.kcore_decompose(10, None, None, None, None) == -1
+    assert "null" in lib.kcore_last_error().decode()
+    with pytest.raises(TypeError):
+        kc_.decompose(torch.zeros(3, dtype=torch.int64, device="cuda"), torch.zeros(2, dtype=torch.int64,
+                                                                                     device="cuda"))
+
+
+def test_validation_mode_rejects_bad_csr(monkeypatch):
+    kc_ = kc()
+    monkeypatch.setenv("KCORE_VALIDATE", "1")
+    rp, ci = sg.to_csr(4, [(0, 1), (1, 2), (2, 3)])
+    assert run_gpu(rp, ci).tolist() == [1, 1, 1, 1]
+    asym_rp = np.array([0, 1, 1, 1, 1], np.int64)
+    asym_ci = np.array([1], np.int32)
+    with pytest.raises(kc_.KcoreError, match="symmetric"):
+        run_gpu(asym_rp, asym_ci)
+    loop_rp = np.array([0, 1, 2], np.int64)
+    loop_ci = np.array([0, 1], np.int32)
+    with pytest.raises(kc_.KcoreError, match="self-loop"):
+        run_gpu(loop_rp, loop_ci)
+    oob_ci = np.array([1, 7], np.int32)
+    with pytest.raises(kc_.KcoreError, match="range"):
+        run_gpu(np.array([0, 1, 2], np.int64), oob_ci)
