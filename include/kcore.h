@@ -57,7 +57,10 @@ typedef struct kcore_tuning {
   int32_t rounds_per_poll; /* rounds enqueued between host checks of the frontier (first chunk) */
   int32_t activation;      /* 0: guarded two-sided rule (default), 1: one-sided rule */
   int32_t timing;          /* 1: bracket every round launch with HIP events (fills the *_ms statistics) */
-  int32_t reserved[8];
+  int32_t list_cap;        /* sparse frontier list capacity per degree class; beyond it the next round
+                              sweeps the round stamps densely (0: library default) */
+  int32_t no_prune;        /* 1: disable the pruned adjacency (always scan the full neighbour list) */
+  int32_t reserved[6];
 } kcore_tuning;
 
 /* Per-call statistics (optional output).  Edge visits count the adjacency
@@ -77,7 +80,9 @@ typedef struct kcore_stats {
   int64_t dense_activations;
   double dense_ms;         /* duration of the dense round kernel (timing mode) */
   double sparse_ms;        /* summed durations of all later round kernels (timing mode) */
-  int64_t reserved[3];
+  int64_t full_scans;      /* recomputations that read the full neighbour list */
+  int64_t prune_writes;    /* entries written to pruned neighbour lists */
+  int64_t dense_rounds;    /* rounds swept densely from the round stamps */
 } kcore_stats;
 
 /*
@@ -89,7 +94,8 @@ typedef struct kcore_stats {
  *             alias row_ptr or col_idx.  Used as the estimate array during the run.
  *   stream    hipStream_t (as void*), NULL for the default stream.
  * All graph buffers are owned by the caller and only read.  The library keeps
- * a per-device workspace (about 9 bytes per vertex plus a small control block),
+ * a per-device workspace (about 21 bytes per vertex plus 4 bytes per adjacency
+ * entry for the pruned neighbour lists, and a small control block),
  * allocated on first use, grown on demand and reused by later calls.
  * Work is enqueued on `stream`; the call returns after the fixpoint has been
  * reached (it synchronises `stream` a few times to test for convergence), so

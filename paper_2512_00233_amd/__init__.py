@@ -44,7 +44,9 @@ class Tuning(ctypes.Structure):
         ("rounds_per_poll", ctypes.c_int32),
         ("activation", ctypes.c_int32),
         ("timing", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 8),
+        ("list_cap", ctypes.c_int32),
+        ("no_prune", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -64,7 +66,9 @@ class Stats(ctypes.Structure):
         ("dense_activations", ctypes.c_int64),
         ("dense_ms", ctypes.c_double),
         ("sparse_ms", ctypes.c_double),
-        ("reserved", ctypes.c_int64 * 3),
+        ("full_scans", ctypes.c_int64),
+        ("prune_writes", ctypes.c_int64),
+        ("dense_rounds", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:

@@ -17,6 +17,8 @@ struct Tuning {
   int poll;       // rounds in the first chunk between host checks
   int one_sided;  // activation rule
   int timing;     // HIP events around every round launch
+  int list_cap;   // sparse list capacity per class
+  int prune;      // pruned adjacency on/off
 };
 
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus);

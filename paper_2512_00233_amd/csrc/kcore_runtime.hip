@@ -39,9 +39,15 @@ struct Workspace {
   int device = -1;
   int num_cus = 0;
   int64_t cap_n = 0;
+  int64_t cap_nnz = 0;
   int32_t* stamp = nullptr;
   uint8_t* cls = nullptr;
   int32_t* lists[2] = {nullptr, nullptr};
+  int32_t* slist = nullptr;
+  int32_t* plen = nullptr;
+  int32_t* plow = nullptr;
+  int32_t* pruned = nullptr;
+  int64_t* host_nnz = nullptr;  // pinned
   Ctl* ctl = nullptr;
   Ctl* host_ctl = nullptr;   // pinned
   int32_t* verr = nullptr;   // validation result (device)
@@ -60,14 +66,15 @@ struct Workspace {
   }
 
   void release() {
-    (void)hipFree(stamp);
-    (void)hipFree(cls);
-    (void)hipFree(lists[0]);
-    (void)hipFree(lists[1]);
+    for (void* p : {(void*)stamp, (void*)cls, (void*)lists[0], (void*)lists[1], (void*)slist, (void*)plen,
+                    (void*)plow, (void*)pruned})
+      (void)hipFree(p);
     stamp = nullptr;
     cls = nullptr;
     lists[0] = lists[1] = nullptr;
+    slist = plen = plow = pruned = nullptr;
     cap_n = 0;
+    cap_nnz = 0;
   }
 };
 
@@ -89,27 +96,36 @@ static kcore_status get_workspace(Workspace** out) {
     KC_HIP(hipHostMalloc(&ws->host_ctl, sizeof(Ctl), hipHostMallocDefault));
     KC_HIP(hipMalloc(&ws->verr, sizeof(int32_t)));
     KC_HIP(hipHostMalloc(&ws->host_verr, sizeof(int32_t), hipHostMallocDefault));
+    KC_HIP(hipHostMalloc(&ws->host_nnz, sizeof(int64_t), hipHostMallocDefault));
     g_ws[dev] = ws;
   }
   *out = g_ws[dev];
   return KCORE_OK;
 }
 
-static kcore_status ensure_capacity(Workspace* ws, int64_t n, hipStream_t st) {
-  if (n <= ws->cap_n) return KCORE_OK;
+static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, hipStream_t st) {
+  if (n <= ws->cap_n && nnz <= ws->cap_nnz) return KCORE_OK;
   KC_HIP(hipStreamSynchronize(st));
+  const int64_t cap = std::max<int64_t>({n, ws->cap_n, 1024});
+  const int64_t cap_e = std::max<int64_t>({nnz, ws->cap_nnz, 1024});
   ws->release();
-  int64_t cap = std::max<int64_t>(n, 1024);
-  if (hipMalloc(&ws->stamp, sizeof(int32_t) * cap) != hipSuccess ||
-      hipMalloc(&ws->cls, sizeof(uint8_t) * cap) != hipSuccess ||
-      hipMalloc(&ws->lists[0], sizeof(int32_t) * cap) != hipSuccess ||
-      hipMalloc(&ws->lists[1], sizeof(int32_t) * cap) != hipSuccess) {
+  bool ok = hipMalloc(&ws->stamp, sizeof(int32_t) * cap) == hipSuccess &&
+            hipMalloc(&ws->cls, sizeof(uint8_t) * cap) == hipSuccess &&
+            hipMalloc(&ws->lists[0], sizeof(int32_t) * cap) == hipSuccess &&
+            hipMalloc(&ws->lists[1], sizeof(int32_t) * cap) == hipSuccess &&
+            hipMalloc(&ws->slist, sizeof(int32_t) * cap) == hipSuccess &&
+            hipMalloc(&ws->plen, sizeof(int32_t) * cap) == hipSuccess &&
+            hipMalloc(&ws->plow, sizeof(int32_t) * cap) == hipSuccess &&
+            hipMalloc(&ws->pruned, sizeof(int32_t) * cap_e) == hipSuccess;
+  if (!ok) {
     (void)hipGetLastError();
     ws->release();
-    return fail(KCORE_E_NOMEM, "workspace allocation failed for n=" + std::to_string(n));
+    return fail(KCORE_E_NOMEM, "workspace allocation failed for n=" + std::to_string(n) +
+                                   " nnz=" + std::to_string(nnz));
   }
   KC_HIP(hipMemsetAsync(ws->stamp, 0, sizeof(int32_t) * cap, st));
   ws->cap_n = cap;
+  ws->cap_nnz = cap_e;
   ws->epoch = 1;
   return KCORE_OK;
 }
@@ -125,6 +141,8 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.poll = 4;
   r.one_sided = 0;
   r.timing = 0;
+  r.list_cap = 8192;
+  r.prune = 1;
   if (const char* e = std::getenv("KCORE_TAIL")) r.tail = std::atoi(e);
   if (t) {
     if (t->thread_max_deg > 0) r.t1 = std::min(t->thread_max_deg, kThreadMaxDeg);
@@ -136,6 +154,8 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
     if (t->rounds_per_poll > 0) r.poll = t->rounds_per_poll;
     r.one_sided = t->activation == 1;
     r.timing = t->timing == 1;
+    if (t->list_cap > 0) r.list_cap = t->list_cap;
+    r.prune = t->no_prune != 1;
   }
   r.t1 = std::max(r.t1, 1);
   r.t2 = std::max(r.t2, r.t1);
@@ -162,7 +182,12 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
   kcore_status s = get_workspace(&ws);
   if (s != KCORE_OK) return s;
   std::lock_guard<std::mutex> lk(ws->mu);
-  s = ensure_capacity(ws, n, st);
+  *ws->host_nnz = 0;
+  KC_HIP(hipMemcpyAsync(ws->host_nnz, row_ptr + n, sizeof(Off), hipMemcpyDeviceToHost, st));
+  KC_HIP(hipStreamSynchronize(st));
+  const int64_t nnz = sizeof(Off) == 8 ? *ws->host_nnz : (int64_t)*(const int32_t*)ws->host_nnz;
+  if (nnz < 0) return fail(KCORE_E_INVALID, "row_ptr[n] is negative");
+  s = ensure_capacity(ws, n, nnz, st);
   if (s != KCORE_OK) return s;
   const Tuning tu = resolve_tuning(tuning, ws->num_cus);
   const int init_grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
@@ -194,12 +219,20 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
   a.cls = ws->cls;
   a.lists[0] = ws->lists[0];
   a.lists[1] = ws->lists[1];
+  a.slist = ws->slist;
+  a.pruned = ws->pruned;
+  a.plen = ws->plen;
+  a.plow = ws->plow;
   a.ctl = ws->ctl;
   a.t1 = tu.t1;
   a.t2 = tu.t2;
   a.t3 = tu.t3;
   a.tail_threshold = tu.tail;
   a.one_sided = tu.one_sided;
+  a.list_cap = tu.list_cap;
+  a.prune = tu.prune;
+  const int32_t collect = stats ? 1 : 0;
+  const int seed_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 8191) / 8192, 1024));
 
   const int32_t r0 = ws->epoch;
   double dense_ms = 0, sparse_ms = 0;
@@ -210,9 +243,9 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
   }
   KC_HIP(hipMemsetAsync(ws->ctl, 0, sizeof(Ctl), st));
   hipLaunchKernelGGL(k_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a);
-  hipLaunchKernelGGL(k_seed<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, r0);
+  hipLaunchKernelGGL(k_seed<Off>, dim3(seed_grid), dim3(kBlock), 0, st, a);
   if (tu.timing) KC_HIP(hipEventRecord(ws->events[0], st));
-  hipLaunchKernelGGL((k_round<kBlock, true, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, r0);
+  hipLaunchKernelGGL((k_round<kBlock, true, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, r0, collect);
   KC_HIP(hipGetLastError());
   if (tu.timing) {
     KC_HIP(hipEventRecord(ws->events[1], st));
@@ -229,7 +262,7 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
   for (;;) {
     for (int i = 0; i < K; ++i) {
       if (tu.timing) KC_HIP(hipEventRecord(ws->events[2 * i], st));
-      hipLaunchKernelGGL((k_round<kBlock, false, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, r + i);
+      hipLaunchKernelGGL((k_round<kBlock, false, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, r + i, collect);
       if (tu.timing) KC_HIP(hipEventRecord(ws->events[2 * i + 1], st));
     }
     KC_HIP(hipGetLastError());
@@ -245,7 +278,7 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
       }
     }
     const int32_t* c = ws->host_ctl->cnt[r % 3];
-    if (c[0] == 0 && c[1] == 0 && c[2] == 0) break;
+    if (ws->host_ctl->overflow[r % 3][0] == 0 && c[0] == 0 && c[1] == 0 && c[2] == 0) break;
     if ((int64_t)r - r0 > (int64_t)1 << 24) return fail(KCORE_E_HIP, "round limit exceeded");
     K = std::min(2 * K, 64);
   }
@@ -266,6 +299,9 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
     stats->dense_activations = (int64_t)dense_st[3];
     stats->dense_ms = dense_ms;
     stats->sparse_ms = sparse_ms;
+    stats->full_scans = (int64_t)hc.stats[ST_FULL_SCANS];
+    stats->prune_writes = (int64_t)hc.stats[ST_PRUNE_WRITES];
+    stats->dense_rounds = (int64_t)hc.stats[ST_DENSE_ROUNDS];
   }
   return KCORE_OK;
 }

@@ -159,6 +159,10 @@ TUNINGS = {
     "lane_only_small": dict(thread_max_deg=2, wave_max_deg=64, block_max_deg=256),
     "all_huge": dict(thread_max_deg=1, wave_max_deg=1, block_max_deg=1),
     "poll_every_round": dict(rounds_per_poll=1, timing=1),
+    "always_dense": dict(list_cap=1, tail_threshold=-1),
+    "always_sparse": dict(list_cap=1 << 30),
+    "no_prune": dict(no_prune=1),
+    "no_prune_one_sided": dict(no_prune=1, activation=1, list_cap=64),
 }
 
 
