@@ -49,18 +49,21 @@ typedef enum {
 /* Tuning knobs of the round kernels.  Zero in a field means "library default".
  * Results never depend on these values; only speed does. */
 typedef struct kcore_tuning {
-  int32_t thread_max_deg;  /* vertices with degree <= this: one lane each (max 8) */
-  int32_t wave_max_deg;    /* <= this: one 64-lane wavefront each (max 1024); above: one workgroup */
-  int32_t block_max_deg;   /* <= this: workgroup keeps values in registers; above: multi-pass search */
-  int32_t tail_threshold;  /* frontier size at or below which one workgroup finishes the run (<0: never) */
-  int32_t grid_blocks;     /* workgroups per round launch (0: 8 per compute unit) */
-  int32_t rounds_per_poll; /* rounds enqueued between host checks of the frontier (first chunk) */
+  int32_t thread_max_deg;  /* class 0, one lane per vertex: degree <= this (1..8, default 8) */
+  int32_t group_max_deg;   /* class 1, 16 lanes per vertex: degree <= this (<= 64, default 64) */
+  int32_t wave_max_deg;    /* class 2, one wavefront per vertex: degree <= this (<= 512, default 512);
+                              above: class 3, one workgroup per vertex */
+  int32_t tail_threshold;  /* frontier work (lane = 1, group = 4, wavefront = 16) at or below which one
+                              workgroup finishes the run (<0: never; default 2048) */
+  int32_t grid_blocks;     /* workgroups per small-class round launch (0: 8 per compute unit) */
+  int32_t big_grid_blocks; /* workgroups per class-3 round launch (0: 4 per compute unit) */
+  int32_t rounds_per_poll; /* rounds enqueued before the first host check of the frontier */
   int32_t activation;      /* 0: guarded two-sided rule (default), 1: one-sided rule */
   int32_t timing;          /* 1: bracket every round launch with HIP events (fills the *_ms statistics) */
-  int32_t list_cap;        /* sparse frontier list capacity per degree class; beyond it the next round
-                              sweeps the round stamps densely (0: library default) */
+  int32_t list_cap;        /* frontier list capacity per degree class; beyond it the next round rebuilds
+                              its lists from the round stamps (0: library default 8192) */
   int32_t no_prune;        /* 1: disable the pruned adjacency (always scan the full neighbour list) */
-  int32_t reserved[6];
+  int32_t reserved[5];
 } kcore_tuning;
 
 /* Per-call statistics (optional output).  Edge visits count the adjacency
@@ -73,7 +76,7 @@ typedef struct kcore_stats {
   int64_t edge_visits;     /* adjacency entries read by those recomputations */
   int64_t changes;         /* estimate decreases */
   int64_t activations;     /* vertices appended to a next frontier */
-  /* first (dense) round alone; filled only when tuning.timing == 1 */
+  /* first round (every vertex of degree >= 2) alone; filled only when tuning.timing == 1 */
   int64_t dense_vertex_updates;
   int64_t dense_edge_visits;
   int64_t dense_changes;
@@ -82,7 +85,8 @@ typedef struct kcore_stats {
   double sparse_ms;        /* summed durations of all later round kernels (timing mode) */
   int64_t full_scans;      /* recomputations that read the full neighbour list */
   int64_t prune_writes;    /* entries written to pruned neighbour lists */
-  int64_t dense_rounds;    /* rounds swept densely from the round stamps */
+  int64_t dense_rounds;    /* rounds whose lists were rebuilt from the round stamps */
+  int64_t reserved2;
 } kcore_stats;
 
 /*

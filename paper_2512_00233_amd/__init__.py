@@ -37,16 +37,17 @@ class Tuning(ctypes.Structure):
     """Mirror of ``kcore_tuning`` (zero = library default)."""
     _fields_ = [
         ("thread_max_deg", ctypes.c_int32),
+        ("group_max_deg", ctypes.c_int32),
         ("wave_max_deg", ctypes.c_int32),
-        ("block_max_deg", ctypes.c_int32),
         ("tail_threshold", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32),
+        ("big_grid_blocks", ctypes.c_int32),
         ("rounds_per_poll", ctypes.c_int32),
         ("activation", ctypes.c_int32),
         ("timing", ctypes.c_int32),
         ("list_cap", ctypes.c_int32),
         ("no_prune", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -69,11 +70,11 @@ class Stats(ctypes.Structure):
         ("full_scans", ctypes.c_int64),
         ("prune_writes", ctypes.c_int64),
         ("dense_rounds", ctypes.c_int64),
+        ("reserved2", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
-        return {name: (getattr(self, name) if name != "reserved" else None) for name, _ in self._fields_
-                if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}
 
 
 def library_path() -> str:

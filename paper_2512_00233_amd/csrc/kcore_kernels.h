@@ -18,19 +18,26 @@
 //    current frontier).  The first clause is the paper's two-sided filter;
 //    the second covers the neighbours whose own value is still moving in this
 //    round, for which x may be stale.  One-sided mode (x > b only) is kept as
-//    an option.
-//  * Frontier membership is a per-vertex round stamp (atomicMax dedup).  A
-//    large frontier is swept densely from the stamps (no shared counters); a
-//    small one is kept as three lists by degree class (lane / wavefront /
-//    workgroup), appended with one atomic per wavefront and capped: overflow
-//    switches the next round to the dense sweep.
+//    an option and used in the first round, where every vertex is active.
+//  * Frontier membership is a per-vertex round stamp (atomicMax dedup).  The
+//    frontier is processed as four lists by degree class (lane <= 8,
+//    16-lane group <= 64, wavefront <= 512, workgroup above).  Activations
+//    append to the next round's lists with one atomic per wavefront, up to a
+//    cap; past the cap the next round rebuilds its lists from the stamps in
+//    one compaction pass (one atomic per workgroup and class).
+//  * The h-index search over values held in registers is k-ary: the first
+//    pass tests e, e-1, e-3, e-7, ... at once (most recomputations stop there),
+//    later passes split the remaining interval evenly.  Long adjacency lists
+//    use a one-pass LDS histogram instead.
 //  * Pruned adjacency: after a full scan that yields h, a vertex of degree
-//    > 8 keeps the neighbours whose estimate is >= L = 3h/4.  Estimates only
+//    > 64 keeps the neighbours whose estimate is >= L = 3h/4.  Estimates only
 //    decrease, so the pruned-away neighbours stay below L forever, and a
 //    search over the pruned list that finds h' >= L is exact; otherwise the
 //    vertex rescans its full adjacency and rebuilds the list.
 //  * When the frontier is small, one workgroup runs all remaining rounds
 //    (the GPU analogue of FastK's switch to sequential processing, Sec. IV).
+//  * Batched graphs: neighbour ids are graph-local; a per-vertex base offset
+//    turns them into global ids (pruned lists store global ids).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,20 +46,28 @@
 namespace kcore {
 
 constexpr int kWave = 64;
-constexpr int kThreadMaxDeg = 8;    // compile-time register budget of the lane path
-constexpr int kWaveRegs = 8;        // values per lane in the wavefront path (<= 512 neighbours)
-constexpr int kBlockRegs = 8;       // values per thread in the workgroup path
-constexpr int kHugeThresholds = 8;  // thresholds per pass of the multi-pass search
+constexpr int kClasses = 4;
+constexpr int kLaneMaxDeg = 8;      // class 0: one lane, registers
+constexpr int kGroupLanes = 16;     // class 1: 16 lanes x 4 values
+constexpr int kGroupRegs = 4;
+constexpr int kGroupMaxDeg = kGroupLanes * kGroupRegs;  // 64
+constexpr int kWaveRegs = 8;        // class 2: 64 lanes x 8 values
+constexpr int kWaveMaxDeg = kWave * kWaveRegs;           // 512
+constexpr int kBigBlock = 256;      // class 3: one workgroup per vertex
+constexpr int kBigRegs = 8;         // values per thread held in registers (2048 per workgroup)
+constexpr int kKary = 8;            // thresholds per pass of the k-ary search
+constexpr int kHistBins = 4096;     // LDS histogram bins of the one-pass search (16 KB)
 
 // Control block in device memory.  Counter slot s = round % 3.
 struct Ctl {
-  int32_t cnt[3][4];       // [slot][class] sparse list sizes (may exceed the cap: then overflow is set)
-  int32_t overflow[3][4];  // [slot][0]: 1 when the round of this slot runs as a dense sweep
-  int32_t tail_cnt[2][4];  // counters of the single-workgroup tail
-  int32_t pop[4];          // vertices per degree class (static list sizes)
+  int32_t cnt[3][kClasses];       // sparse list sizes per class (may exceed the cap: then overflow is set)
+  int32_t overflow[3][4];         // [slot][0]: 1 when the round of this slot rebuilds its lists by compaction
+  int32_t ccnt[2][kClasses];      // list sizes produced by the compaction pass, by round parity
+  int32_t tail_cnt[2][kClasses];  // counters of the single-workgroup tail
+  int32_t pop[kClasses];          // vertices per degree class (list region sizes)
+  int32_t seed_fill[kClasses];    // first-round (static) list sizes: vertices of degree >= 2 per class
   unsigned long long stats[16];
-  int32_t error;           // 1: the tail hit its round cap
-  int32_t seed_fill[4];    // static-list fill counters of k_seed
+  int32_t error;                  // 1: the tail hit its round cap
   int32_t pad[3];
 };
 enum Stat {
@@ -70,16 +85,16 @@ struct Args {
   int64_t n;
   const Off* row_ptr;
   const int32_t* col;
+  const int32_t* vbase;  // batched graphs: global id of the first vertex of each vertex's graph (nullptr: 0)
   int32_t* est;
   int32_t* stamp;
   uint8_t* cls;
-  int32_t* lists[2];  // sparse frontier lists by parity of the round (class regions at prefix offsets of pop)
-  int32_t* slist;     // static lists: all class-1 vertices, then all class-2 vertices
-  int32_t* pruned;    // pruned adjacency, same row offsets as col
+  int32_t* lists[2];  // frontier lists by parity of the round (class regions at prefix offsets of pop)
+  int32_t* slist;     // first-round lists: vertices of degree >= 2, same class regions
+  int32_t* pruned;    // pruned adjacency (global ids), same row offsets as col
   int32_t* plen;      // pruned list length (0: none yet)
   int32_t* plow;      // pruned list threshold L
   Ctl* ctl;
-  int32_t t1, t2, t3;  // thread / wave / block degree limits
   int32_t tail_threshold;
   int32_t list_cap;    // sparse list capacity per class before overflow
   int32_t one_sided;

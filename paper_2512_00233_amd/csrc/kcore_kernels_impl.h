@@ -27,7 +27,7 @@ __device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
   const int lane = lane_id();
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
-    int32_t t = __shfl_up(x, o);
+    const int32_t t = __shfl_up(x, o);
     if (lane >= o) x += t;
   }
   return x;
@@ -38,44 +38,48 @@ __device__ __forceinline__ int32_t* list_of(const Args<Off>& a, int32_t round) {
   return (round & 1) ? a.lists[1] : a.lists[0];  // select, not an indexed load from the argument struct
 }
 
+__device__ __forceinline__ void region_bases(const Ctl* ctl, int32_t (&b)[kClasses]) {
+  int32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kClasses; ++k) {
+    b[k] = acc;
+    acc += ctl->pop[k];
+  }
+}
+
 struct LaneStats {
   uint64_t v[kLaneStats] = {0, 0, 0, 0, 0, 0};
 };
 
 // Where activated vertices go.
 struct Sink {
-  int32_t* list;      // next sparse frontier list
-  int32_t* cnt;       // its three class counters
-  int32_t* overflow;  // flag of the next round (nullptr: never overflows)
+  int32_t* list;      // next frontier list
+  int32_t* cnt;       // its class counters
+  int32_t* overflow;  // flag of the next round (nullptr: uncapped, never overflows)
   int32_t stamp;      // round number of the next frontier
-  int32_t b[3];       // class region offsets in the list
-  int32_t cap[3];     // class capacities
+  int32_t b[kClasses];
+  int32_t cap[kClasses];
 };
 
 template <typename Off>
 __device__ __forceinline__ Sink make_sink(const Args<Off>& a, int32_t next_round, int32_t* cnt, int32_t* overflow,
                                           bool capped) {
-  const Ctl* ctl = a.ctl;
   Sink s;
   s.list = list_of(a, next_round);
   s.cnt = cnt;
   s.overflow = overflow;
   s.stamp = next_round;
-  const int32_t p0 = ctl->pop[0], p1 = ctl->pop[1], p2 = ctl->pop[2];
-  s.b[0] = 0;
-  s.b[1] = p0;
-  s.b[2] = p0 + p1;
-  s.cap[0] = capped ? min(p0, a.list_cap) : p0;
-  s.cap[1] = capped ? min(p1, a.list_cap) : p1;
-  s.cap[2] = capped ? min(p2, a.list_cap) : p2;
+  region_bases(a.ctl, s.b);
+#pragma unroll
+  for (int k = 0; k < kClasses; ++k) s.cap[k] = capped ? min(a.ctl->pop[k], a.list_cap) : a.ctl->pop[k];
   return s;
 }
 
 // Activate up to N candidates per lane for the next round: deduplicate on the
 // round stamp (all atomics of a lane in flight together), then, unless the next
-// round already overflowed to a dense sweep, append the winners to the list of
-// their degree class with one atomic per class per wavefront.  Every active lane
-// of the wavefront must call this.
+// round already rebuilds its lists by compaction, append the winners to the
+// list of their degree class with one atomic per class per wavefront.  Every
+// active lane of the wavefront must call this.
 template <int N, typename Off>
 __device__ __forceinline__ void activate_batch(const Args<Off>& a, const Sink& s, const int32_t (&v)[N],
                                                const bool (&want)[N], LaneStats& st) {
@@ -92,13 +96,13 @@ __device__ __forceinline__ void activate_batch(const Args<Off>& a, const Sink& s
 #pragma unroll
   for (int i = 0; i < N; ++i) first |= (p[i] < s.stamp ? 1u : 0u) << i;
   st.v[ST_ACTIVATIONS] += __popc(first);
-  const bool dense_next = s.overflow && *(volatile int32_t*)s.overflow;
-  if (dense_next || !ballot(first != 0)) return;
+  const bool compact_next = s.overflow && *(volatile int32_t*)s.overflow;
+  if (compact_next || !ballot(first != 0)) return;
 #pragma unroll
-  for (int i = 0; i < N; ++i) p[i] = (first >> i & 1u) ? (int32_t)a.cls[v[i]] : 3;  // degree class of winners
+  for (int i = 0; i < N; ++i) p[i] = (first >> i & 1u) ? (int32_t)a.cls[v[i]] : kClasses;  // class of winners
   const int lane = lane_id();
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < kClasses; ++k) {
     int32_t mine = 0;
 #pragma unroll
     for (int i = 0; i < N; ++i) mine += p[i] == k;
@@ -123,44 +127,123 @@ __device__ __forceinline__ void activate_batch(const Args<Off>& a, const Sink& s
 // Should neighbour v, whose estimate read in this round is x, be activated
 // after the current vertex dropped from e to h?
 template <typename Off>
-__device__ __forceinline__ bool wants(const Args<Off>& a, int32_t v, int32_t x, int32_t e, int32_t h, bool dense,
-                                      int32_t round) {
+__device__ __forceinline__ bool decide(const Args<Off>& a, int32_t v, int32_t x, int32_t e, int32_t h, bool dense,
+                                       int32_t round) {
   if (x <= h) return false;
   if (a.one_sided || x <= e || dense) return true;
-  return a.stamp[v] >= round;  // v is in the current frontier: its value may still be moving
+  return a.stamp[v] == round;  // in the current frontier (its value may still move) and not yet re-activated
 }
 
-// ------------------------------------------------------------------ lane path
-// One lane per vertex, degree <= kThreadMaxDeg, values held in registers.
-template <typename Off>
+// ------------------------------------------------------------------ k-ary search over register values
+// Each group of G lanes holds R values per lane.  Returns, per group, the
+// largest k in [lo, e] with |{values >= k}| >= k, or lo - 1 when that count at
+// lo is below lo (possible only when the caller does not know count(lo) >= lo).
+// Pass 1 tests e, e-1, e-3, e-7, ..., lo; later passes cut the remaining
+// interval into kKary pieces.  Every lane of the wavefront must call this.
+template <int G, int R>
+__device__ __forceinline__ int32_t kary_regs(const int32_t (&x)[R], int32_t e, int32_t lo, bool active) {
+  constexpr int S = kKary;
+  const int lane = lane_id();
+  const uint64_t gm = (G == kWave) ? ~0ull : (((1ull << G) - 1) << (lane & ~(G - 1)));
+  int32_t hi = e, res = lo - 1;
+  bool done = !active, first = true;
+  while (ballot(!done)) {
+    int32_t t[S];
+    if (first) {
+#pragma unroll
+      for (int q = 0; q < S - 1; ++q) t[q] = max(lo, e - ((1 << q) - 1));
+      t[S - 1] = lo;
+    } else {
+      const int32_t span = hi - lo;
+      const int32_t step = (span + S - 1) / S;
+#pragma unroll
+      for (int q = 0; q < S; ++q) t[q] = lo + (int32_t)min((int64_t)span, (int64_t)(q + 1) * step);
+    }
+    int32_t c[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) c[q] = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int q = 0; q < S; ++q) c[q] += popc(ballot(x[r] >= t[q]) & gm);
+    if (!done) {
+      if (first) {
+        int qs = -1;  // thresholds descend: the first hit is the largest satisfied value
+#pragma unroll
+        for (int q = S - 1; q >= 0; --q)
+          if (c[q] >= t[q]) qs = q;
+        if (qs < 0) {
+          done = true;
+        } else {
+          int32_t nhi = e, nlo = t[0];
+#pragma unroll
+          for (int q = 1; q < S; ++q)
+            if (q == qs) {
+              nhi = t[q - 1] - 1;
+              nlo = t[q];
+            }
+          lo = nlo;
+          hi = nhi;
+        }
+        first = false;
+      } else {
+        int qs = -1;  // thresholds ascend: the last hit is the largest satisfied value
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+          if (c[q] >= t[q]) qs = q;
+        if (qs < 0) {
+          hi = t[0] - 1;
+        } else {
+          int32_t nlo = t[0], nhi = hi;
+#pragma unroll
+          for (int q = 0; q < S; ++q) {
+            if (q == qs) nlo = t[q];
+            if (q == qs + 1) nhi = t[q] - 1;
+          }
+          lo = nlo;
+          hi = nhi;
+        }
+      }
+      if (!done && lo >= hi) {
+        res = lo;
+        done = true;
+      }
+    }
+  }
+  return res;
+}
+
+// ------------------------------------------------------------------ class 0: lane per vertex
+template <bool BATCH, typename Off>
 __device__ __forceinline__ void upd_lane(const Args<Off>& a, const Sink& s, int32_t u, bool valid, bool dense,
                                          int32_t round, LaneStats& st) {
-  int32_t e = 0, d = 0;
+  int32_t e = 0, d = 0, gb = 0;
   Off beg = 0;
   if (valid) {
     beg = a.row_ptr[u];
     d = (int32_t)(a.row_ptr[u + 1] - beg);
     e = a.est[u];
+    if (BATCH) gb = a.vbase[u];
   }
   valid = valid && e >= 2;  // an estimate of 1 is final: every non-isolated vertex has coreness >= 1
-  int32_t c[kThreadMaxDeg], x[kThreadMaxDeg];
+  int32_t c[kLaneMaxDeg], x[kLaneMaxDeg];
 #pragma unroll
-  for (int i = 0; i < kThreadMaxDeg; ++i) c[i] = (valid && i < d) ? a.col[beg + i] : 0;
+  for (int i = 0; i < kLaneMaxDeg; ++i) c[i] = (valid && i < d) ? gb + a.col[beg + i] : 0;
 #pragma unroll
-  for (int i = 0; i < kThreadMaxDeg; ++i) x[i] = (valid && i < d) ? a.est[c[i]] : 0;
+  for (int i = 0; i < kLaneMaxDeg; ++i) x[i] = (valid && i < d) ? a.est[c[i]] : 0;
   int32_t h = e;
   if (valid) {
     st.v[ST_UPDATES] += 1;
     st.v[ST_VISITS] += (uint64_t)d;
     int cnt = 0;
 #pragma unroll
-    for (int i = 0; i < kThreadMaxDeg; ++i) cnt += x[i] >= e;
+    for (int i = 0; i < kLaneMaxDeg; ++i) cnt += x[i] >= e;
     if (cnt < e) {
       h = 1;
       for (int k = e - 1; k >= 2; --k) {
         int sk = 0;
 #pragma unroll
-        for (int i = 0; i < kThreadMaxDeg; ++i) sk += x[i] >= k;
+        for (int i = 0; i < kLaneMaxDeg; ++i) sk += x[i] >= k;
         if (sk >= k) {
           h = k;
           break;
@@ -172,16 +255,55 @@ __device__ __forceinline__ void upd_lane(const Args<Off>& a, const Sink& s, int3
   }
   const bool changed = valid && h < e;
   if (!ballot(changed)) return;
-  bool w[kThreadMaxDeg];
+  bool w[kLaneMaxDeg];
 #pragma unroll
-  for (int i = 0; i < kThreadMaxDeg; ++i) w[i] = changed && i < d && wants(a, c[i], x[i], e, h, dense, round);
-  activate_batch<kThreadMaxDeg>(a, s, c, w, st);
+  for (int i = 0; i < kLaneMaxDeg; ++i) w[i] = changed && i < d && decide(a, c[i], x[i], e, h, dense, round);
+  activate_batch<kLaneMaxDeg>(a, s, c, w, st);
 }
 
-// ------------------------------------------------------------------ wavefront path
-// One 64-lane wavefront per vertex, degree <= 64 * kWaveRegs; searches its
-// pruned list first when it has one.
-template <typename Off>
+// ------------------------------------------------------------------ class 1: 16-lane group per vertex
+template <bool BATCH, typename Off>
+__device__ __forceinline__ void upd_group(const Args<Off>& a, const Sink& s, int32_t u, bool valid, bool dense,
+                                          int32_t round, LaneStats& st) {
+  constexpr int G = kGroupLanes, R = kGroupRegs;
+  const int gl = lane_id() & (G - 1);
+  int32_t e = 0, d = 0, gb = 0;
+  Off beg = 0;
+  if (valid) {
+    beg = a.row_ptr[u];
+    d = (int32_t)(a.row_ptr[u + 1] - beg);
+    e = a.est[u];
+    if (BATCH) gb = a.vbase[u];
+  }
+  valid = valid && e >= 2;
+  int32_t c[R], x[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = gl + G * r;
+    c[r] = (valid && j < d) ? gb + a.col[beg + j] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) x[r] = (valid && gl + G * r < d) ? a.est[c[r]] : 0;
+  if (valid && gl == 0) {
+    st.v[ST_UPDATES] += 1;
+    st.v[ST_VISITS] += (uint64_t)d;
+  }
+  const int32_t h = kary_regs<G, R>(x, e, 1, valid);
+  const bool changed = valid && h < e;
+  if (changed && gl == 0) {
+    a.est[u] = h;
+    st.v[ST_CHANGES] += 1;
+  }
+  if (!ballot(changed)) return;
+  bool w[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) w[r] = changed && (gl + G * r < d) && decide(a, c[r], x[r], e, h, dense, round);
+  activate_batch<R>(a, s, c, w, st);
+}
+
+// ------------------------------------------------------------------ class 2: wavefront per vertex
+// Searches its pruned list first when it has one.
+template <bool BATCH, typename Off>
 __device__ __forceinline__ void upd_wave(const Args<Off>& a, const Sink& s, int32_t u, bool dense, int32_t round,
                                          LaneStats& st) {
   constexpr int R = kWaveRegs;
@@ -190,16 +312,17 @@ __device__ __forceinline__ void upd_wave(const Args<Off>& a, const Sink& s, int3
   const int32_t d = uni((int32_t)(a.row_ptr[u + 1] - beg));
   const int32_t e = uni(a.est[u]);
   if (e < 2) return;
+  const int32_t gb = BATCH ? uni(a.vbase[u]) : 0;
   const int32_t pl = a.prune ? uni(a.plen[u]) : 0;
   const int32_t L = pl > 0 ? uni(a.plow[u]) : 1;
   int32_t c[R], x[R];
   int32_t len = 0;
-  auto load = [&](const int32_t* src, int32_t n_) {
+  auto load = [&](const int32_t* src, int32_t n_, int32_t off) {
     len = n_;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int j = lane + kWave * i;
-      c[i] = (kWave * i < n_ && j < n_) ? src[beg + j] : 0;
+      c[i] = (kWave * i < n_ && j < n_) ? off + src[beg + j] : 0;
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) {
@@ -207,36 +330,21 @@ __device__ __forceinline__ void upd_wave(const Args<Off>& a, const Sink& s, int3
       x[i] = (kWave * i < n_ && j < n_) ? a.est[c[i]] : 0;
     }
   };
-  auto count = [&](int32_t k) {
-    int tot = 0;
-#pragma unroll
-    for (int i = 0; i < R; ++i)
-      if (kWave * i < len) tot += popc(ballot(x[i] >= k));
-    return tot;
-  };
-  auto search = [&](int32_t lo, int32_t hi) {  // max k in [lo, hi] with count(k) >= k, given count(lo) >= lo
-    while (lo < hi) {
-      const int32_t mid = (lo + hi + 1) >> 1;
-      if (count(mid) >= mid) lo = mid;
-      else hi = mid - 1;
-    }
-    return lo;
-  };
   if (lane == 0) st.v[ST_UPDATES] += 1;
   int32_t h = -1;
   if (pl > 0) {
-    load(a.pruned, pl);
+    load(a.pruned, pl, 0);
     if (lane == 0) st.v[ST_VISITS] += pl;
-    if (count(e) >= e) h = e;
-    else if (count(L) >= L) h = search(L, e - 1);
+    const int32_t hp = kary_regs<kWave, R>(x, e, L, true);
+    if (hp >= L) h = hp;
   }
   if (h < 0) {
-    load(a.col, d);
+    load(a.col, d, gb);
     if (lane == 0) {
       st.v[ST_VISITS] += d;
       st.v[ST_FULL_SCANS] += 1;
     }
-    h = count(e) >= e ? e : search(1, e - 1);
+    h = kary_regs<kWave, R>(x, e, 1, true);
     if (a.prune) {
       const int32_t L2 = max(2, (3 * h) / 4);
       int32_t off = 0;
@@ -263,12 +371,11 @@ __device__ __forceinline__ void upd_wave(const Args<Off>& a, const Sink& s, int3
   }
   bool w[R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) w[i] = (lane + kWave * i < len) && wants(a, c[i], x[i], e, h, dense, round);
+  for (int i = 0; i < R; ++i) w[i] = (lane + kWave * i < len) && decide(a, c[i], x[i], e, h, dense, round);
   activate_batch<R>(a, s, c, w, st);
 }
 
-// ------------------------------------------------------------------ workgroup paths
-// Sum over the workgroup of one value per wavefront (lane 0 holds it).
+// ------------------------------------------------------------------ class 3: workgroup per vertex
 template <int BLOCK>
 __device__ __forceinline__ int32_t block_sum_waves(int32_t wave_val, int32_t* red) {
   const int wave = threadIdx.x / kWave;
@@ -300,35 +407,108 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t& total, in
   return before + incl - x;
 }
 
+// Workgroup version of kary_regs (the whole workgroup is one group); red holds
+// kKary * (BLOCK / 64) ints.
+template <int BLOCK, int R>
+__device__ __forceinline__ int32_t kary_block(const int32_t (&x)[R], int32_t e, int32_t lo, int32_t* red) {
+  constexpr int S = kKary;
+  constexpr int NW = BLOCK / kWave;
+  const int wave = threadIdx.x / kWave;
+  int32_t hi = e;
+  bool first = true;
+  for (;;) {
+    int32_t t[S];
+    if (first) {
+#pragma unroll
+      for (int q = 0; q < S - 1; ++q) t[q] = max(lo, e - ((1 << q) - 1));
+      t[S - 1] = lo;
+    } else {
+      const int32_t span = hi - lo;
+      const int32_t step = (span + S - 1) / S;
+#pragma unroll
+      for (int q = 0; q < S; ++q) t[q] = lo + (int32_t)min((int64_t)span, (int64_t)(q + 1) * step);
+    }
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      int32_t cq = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) cq += popc(ballot(x[r] >= t[q]));
+      if (lane_id() == 0) red[q * NW + wave] = cq;
+    }
+    __syncthreads();
+    int32_t c[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      int32_t tot = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) tot += red[q * NW + w];
+      c[q] = tot;
+    }
+    __syncthreads();
+    if (first) {
+      int qs = -1;
+#pragma unroll
+      for (int q = S - 1; q >= 0; --q)
+        if (c[q] >= t[q]) qs = q;
+      if (qs < 0) return lo - 1;
+      int32_t nhi = e, nlo = t[0];
+#pragma unroll
+      for (int q = 1; q < S; ++q)
+        if (q == qs) {
+          nhi = t[q - 1] - 1;
+          nlo = t[q];
+        }
+      lo = nlo;
+      hi = nhi;
+      first = false;
+    } else {
+      int qs = -1;
+#pragma unroll
+      for (int q = 0; q < S; ++q)
+        if (c[q] >= t[q]) qs = q;
+      if (qs < 0) {
+        hi = t[0] - 1;
+      } else {
+        int32_t nlo = t[0], nhi = hi;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+          if (q == qs) nlo = t[q];
+          if (q == qs + 1) nhi = t[q] - 1;
+        }
+        lo = nlo;
+        hi = nhi;
+      }
+    }
+    if (lo >= hi) return lo;
+  }
+}
+
 // Workgroup-wide search over a list in global memory, re-read on each pass:
-// the largest k in [lo, hi] with |{j < len : est[src[j]] >= k}| >= k, or lo - 1
-// when count(lo) < lo.  Each pass tests kHugeThresholds thresholds.
+// the largest k in [lo, hi] with count(k) >= k, or lo - 1 when count(lo) < lo.
+// Each pass tests kKary thresholds (used only for cores above kHistBins).
 template <int BLOCK, typename Off>
-__device__ __forceinline__ int32_t mp_search(const Args<Off>& a, const int32_t* src, int32_t len, int32_t lo,
-                                             int32_t hi, int32_t* red) {
-  constexpr int S = kHugeThresholds;
+__device__ __forceinline__ int32_t mp_search(const Args<Off>& a, const int32_t* src, int32_t off, int32_t len,
+                                             int32_t lo, int32_t hi, int32_t* red) {
+  constexpr int S = kKary;
   constexpr int NW = BLOCK / kWave;
   const int tid = threadIdx.x;
   bool lo_known = false;
   while (!(lo_known && lo >= hi)) {
-    // unknown lo: thr(0) = lo and the rest spread over (lo, hi]; known lo: spread over (lo, hi]
     const int first = lo_known ? 0 : 1;
     const int slots = S - first;
     const int64_t span = (int64_t)hi - lo;
-    auto thr = [&](int q) -> int32_t {
-      if (q < first) return lo;
-      const int r = q - first;
-      if (span >= slots) return (int32_t)(lo + ((int64_t)(r + 1) * span + slots - 1) / slots);
-      return (r < span) ? lo + 1 + r : INT32_MAX;
-    };
     int32_t t[S], cnt[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) {
-      t[q] = uni(thr(q));
+      int32_t tq;
+      if (q < first) tq = lo;
+      else if (span >= slots) tq = (int32_t)(lo + ((int64_t)(q - first + 1) * span + slots - 1) / slots);
+      else tq = (q - first < span) ? lo + 1 + (q - first) : INT32_MAX;
+      t[q] = uni(tq);
       cnt[q] = 0;
     }
     for (int32_t j = tid; j < len; j += BLOCK) {
-      const int32_t xv = a.est[src[j]];
+      const int32_t xv = a.est[off + src[j]];
 #pragma unroll
       for (int q = 0; q < S; ++q) cnt[q] += xv >= t[q];
     }
@@ -354,42 +534,109 @@ __device__ __forceinline__ int32_t mp_search(const Args<Off>& a, const int32_t* 
       lo_known = true;
     }
     if (best < 0) {
-      hi = thr(0) - 1;
+      hi = t[0] - 1;
     } else {
-      const int32_t nlo = thr(best);
-      if (best + 1 < S && thr(best + 1) != INT32_MAX) hi = thr(best + 1) - 1;
+      int32_t nlo = t[0], nhi = hi;
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        if (q == best) nlo = t[q];
+        if (q == best + 1 && t[q] != INT32_MAX) nhi = t[q] - 1;
+      }
       lo = nlo;
+      hi = nhi;
     }
   }
   return lo;
 }
 
-// One workgroup per vertex (degree class 2).  Lists of up to BLOCK * kBlockRegs
-// entries are held in registers (binary search with wavefront ballots);
-// longer ones use the multi-pass search.  The pruned list is tried first.
+// One-pass search over a long list in global memory: the largest k in [lo, e]
+// with count(k) >= k, or lo - 1.  Values in [lo, top] (top = min(e, lo +
+// kHistBins - 1)) go to an LDS histogram, larger ones to one counter; if the
+// answer lies above top, the multi-pass search finishes over (top, e].
 template <int BLOCK, typename Off>
+__device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t* src, int32_t off, int32_t len,
+                                               int32_t lo, int32_t e, int32_t* red, int32_t* hist) {
+  constexpr int U = 4;  // loads in flight per thread
+  const int tid = threadIdx.x;
+  const int32_t top = (int32_t)min((int64_t)e, (int64_t)lo + kHistBins - 1);
+  const int32_t nb = top - lo + 1;
+  for (int32_t i = tid; i < nb; i += BLOCK) hist[i] = 0;
+  __syncthreads();
+  int32_t above = 0;
+  for (int32_t j0 = 0; j0 < len; j0 += BLOCK * U) {
+    int32_t c[U], x[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int32_t j = j0 + q * BLOCK + tid;
+      c[q] = j < len ? off + src[j] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) x[q] = c[q] >= 0 ? a.est[c[q]] : -1;
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      if (x[q] > top) above += 1;
+      else if (x[q] >= lo) atomicAdd(&hist[x[q] - lo], 1);
+    }
+  }
+  const int32_t tot_above = block_sum_waves<BLOCK>(wave_sum(above), red);
+  // thread t owns bins [t*pb, t*pb + pb): suffix sums, then the highest k with count(k) >= k
+  const int32_t pb = (nb + BLOCK - 1) / BLOCK;
+  const int32_t b0 = tid * pb, b1 = min(nb, b0 + pb);
+  int32_t local = 0;
+  for (int32_t b = b0; b < b1; ++b) local += hist[b];
+  int32_t total = 0;
+  const int32_t before = block_excl_scan<BLOCK>(local, total, red);
+  int32_t run = tot_above + (total - before - local);  // values above my bins
+  int32_t cand = -1;
+  for (int32_t b = b1 - 1; b >= b0; --b) {
+    run += hist[b];
+    if (run >= lo + b) {
+      cand = lo + b;
+      break;
+    }
+  }
+  int32_t wm = cand;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) wm = max(wm, __shfl_xor(wm, o));
+  const int wave = tid / kWave;
+  if (lane_id() == 0) red[wave] = wm;
+  __syncthreads();
+  int32_t best = -1;
+#pragma unroll
+  for (int w = 0; w < BLOCK / kWave; ++w) best = max(best, red[w]);
+  __syncthreads();
+  if (top < e && tot_above >= top + 1) return mp_search<BLOCK>(a, src, off, len, top + 1, e, red);
+  return best >= lo ? best : lo - 1;
+}
+
+// One workgroup per vertex of class 3.  Lists of up to BLOCK * kBigRegs entries
+// are held in registers (k-ary search); longer ones use the one-pass LDS
+// histogram.  The pruned list is tried first.
+template <int BLOCK, bool BATCH, typename Off>
 __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32_t u, bool dense, int32_t round,
-                                        LaneStats& st, int32_t* red) {
-  constexpr int R = kBlockRegs;
+                                        LaneStats& st, int32_t* red, int32_t* hist) {
+  constexpr int R = kBigRegs;
   constexpr int CAPR = BLOCK * R;
   const int tid = threadIdx.x;
   const Off beg = a.row_ptr[u];
   const int32_t d = uni((int32_t)(a.row_ptr[u + 1] - beg));
   const int32_t e = uni(a.est[u]);
   if (e < 2) return;
+  const int32_t gb = BATCH ? uni(a.vbase[u]) : 0;
   const int32_t pl = a.prune ? uni(a.plen[u]) : 0;
   const int32_t L = pl > 0 ? uni(a.plow[u]) : 1;
   int32_t c[R], x[R];
-  int32_t len = 0;
+  int32_t len = 0, soff = 0;
   bool inreg = false;
   const int32_t* src = a.col;
-  auto load = [&](const int32_t* from, int32_t n_) {
+  auto load = [&](const int32_t* from, int32_t n_, int32_t off) {
     len = n_;
     src = from;
+    soff = off;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int j = tid + BLOCK * i;
-      c[i] = (BLOCK * i < n_ && j < n_) ? from[beg + j] : 0;
+      c[i] = (BLOCK * i < n_ && j < n_) ? off + from[beg + j] : 0;
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) {
@@ -397,35 +644,21 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
       x[i] = (BLOCK * i < n_ && j < n_) ? a.est[c[i]] : 0;
     }
   };
-  auto count = [&](int32_t k) {
-    int tot = 0;
-#pragma unroll
-    for (int i = 0; i < R; ++i)
-      if (BLOCK * i < len) tot += popc(ballot(x[i] >= k));
-    return block_sum_waves<BLOCK>(tot, red);
-  };
-  auto search = [&](int32_t lo, int32_t hi) {
-    while (lo < hi) {
-      const int32_t mid = (lo + hi + 1) >> 1;
-      if (count(mid) >= mid) lo = mid;
-      else hi = mid - 1;
-    }
-    return lo;
-  };
   if (tid == 0) st.v[ST_UPDATES] += 1;
   int32_t h = -1;
   if (pl > 0) {
     if (tid == 0) st.v[ST_VISITS] += pl;
     if (pl <= CAPR) {
-      load(a.pruned, pl);
+      load(a.pruned, pl, 0);
       inreg = true;
-      if (count(e) >= e) h = e;
-      else if (count(L) >= L) h = search(L, e - 1);
+      const int32_t hp = kary_block<BLOCK, R>(x, e, L, red);
+      if (hp >= L) h = hp;
     } else {
       inreg = false;
       len = pl;
       src = a.pruned;
-      const int32_t hp = mp_search<BLOCK>(a, a.pruned + beg, pl, L, e, red);
+      soff = 0;
+      const int32_t hp = hist_search<BLOCK>(a, a.pruned + beg, 0, pl, L, e, red, hist);
       if (hp >= L) h = hp;
     }
   }
@@ -436,9 +669,9 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
       st.v[ST_FULL_SCANS] += 1;
     }
     if (d <= CAPR) {
-      load(a.col, d);
+      load(a.col, d, gb);
       inreg = true;
-      h = count(e) >= e ? e : search(1, e - 1);
+      h = kary_block<BLOCK, R>(x, e, 1, red);
       if (a.prune) {
         const int32_t L2 = max(2, (3 * h) / 4);
         int32_t mine = 0;
@@ -459,7 +692,8 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
       inreg = false;
       len = d;
       src = a.col;
-      h = mp_search<BLOCK>(a, a.col + beg, d, 1, e, red);
+      soff = gb;
+      h = hist_search<BLOCK>(a, a.col + beg, gb, d, 1, e, red, hist);
       rebuild_pass = a.prune != 0;
     }
   }
@@ -472,7 +706,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
   if (inreg) {
     bool w[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) w[i] = (tid + BLOCK * i < len) && wants(a, c[i], x[i], e, h, dense, round);
+    for (int i = 0; i < R; ++i) w[i] = (tid + BLOCK * i < len) && decide(a, c[i], x[i], e, h, dense, round);
     activate_batch<R>(a, s, c, w, st);
     return;
   }
@@ -484,7 +718,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
     int32_t v[1] = {0};
     int32_t xv = 0;
     if (j < len) {
-      v[0] = src[beg + j];
+      v[0] = soff + src[beg + j];
       xv = a.est[v[0]];
     }
     if (rebuild_pass) {
@@ -495,7 +729,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
       written += total;
     }
     if (changed) {
-      bool w[1] = {(j < len) && wants(a, v[0], xv, e, h, dense, round)};
+      bool w[1] = {(j < len) && decide(a, v[0], xv, e, h, dense, round)};
       activate_batch<1>(a, s, v, w, st);
     }
   }
@@ -503,6 +737,61 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
     a.plen[u] = written;
     a.plow[u] = L2;
     st.v[ST_PRUNE_WRITES] += written;
+  }
+}
+
+// Class-3 vertex inside the single-workgroup tail (rare: the tail starts only
+// without class-3 vertices): multi-pass search over the pruned list (or the
+// full list when it fails), then one streaming activation pass.  Uses few
+// registers; a full-list result below the pruned threshold drops the pruned list.
+template <int BLOCK, bool BATCH, typename Off>
+__device__ __forceinline__ void upd_big_lite(const Args<Off>& a, const Sink& s, int32_t u, int32_t round,
+                                             LaneStats& st, int32_t* red) {
+  const int tid = threadIdx.x;
+  const Off beg = a.row_ptr[u];
+  const int32_t d = uni((int32_t)(a.row_ptr[u + 1] - beg));
+  const int32_t e = uni(a.est[u]);
+  if (e < 2) return;
+  const int32_t gb = BATCH ? uni(a.vbase[u]) : 0;
+  const int32_t pl = a.prune ? uni(a.plen[u]) : 0;
+  const int32_t L = pl > 0 ? uni(a.plow[u]) : 1;
+  if (tid == 0) st.v[ST_UPDATES] += 1;
+  int32_t h = -1;
+  const int32_t* src = a.col + beg;
+  int32_t len = d, off = gb;
+  if (pl > 0) {
+    if (tid == 0) st.v[ST_VISITS] += pl;
+    h = mp_search<BLOCK>(a, a.pruned + beg, 0, pl, L, e, red);
+    if (h >= L) {
+      src = a.pruned + beg;
+      len = pl;
+      off = 0;
+    } else {
+      h = -1;
+    }
+  }
+  if (h < 0) {
+    if (tid == 0) {
+      st.v[ST_VISITS] += d;
+      st.v[ST_FULL_SCANS] += 1;
+      if (pl > 0) a.plen[u] = 0;
+    }
+    h = mp_search<BLOCK>(a, a.col + beg, gb, d, 1, e, red);
+  }
+  if (h == e) return;
+  if (tid == 0) {
+    a.est[u] = h;
+    st.v[ST_CHANGES] += 1;
+  }
+  for (int32_t j0 = 0; j0 < len; j0 += BLOCK) {
+    const int32_t j = j0 + tid;
+    int32_t v[1] = {0};
+    bool w[1] = {false};
+    if (j < len) {
+      v[0] = off + src[j];
+      w[0] = decide(a, v[0], a.est[v[0]], e, h, false, round);
+    }
+    activate_batch<1>(a, s, v, w, st);
   }
 }
 
@@ -524,105 +813,48 @@ __device__ __forceinline__ void flush_stats(Ctl* ctl, const LaneStats& st, unsig
   }
 }
 
-// ------------------------------------------------------------------ frontier sweeps
-// Sparse round: the three class lists of the current round.
-template <int BLOCK, typename Off>
-__device__ __forceinline__ void sweep_lists(const Args<Off>& a, const Sink& s, const int32_t* cur, int32_t n0,
-                                            int32_t n1, int32_t n2, int32_t round, int32_t b1, int32_t b2,
-                                            int32_t worker, int32_t workers, LaneStats& st, int32_t* red) {
-  constexpr int NW = BLOCK / kWave;
-  for (int32_t i = worker; i < n2; i += workers) upd_big<BLOCK>(a, s, cur[b2 + i], false, round, st, red);
-  const int32_t gw = worker * NW + threadIdx.x / kWave;
-  for (int32_t i = gw; i < n1; i += workers * NW) upd_wave(a, s, cur[b1 + i], false, round, st);
-  for (int32_t i = worker * BLOCK + threadIdx.x; i - lane_id() < n0; i += workers * BLOCK) {
-    const bool valid = i < n0;
-    upd_lane(a, s, valid ? cur[i] : 0, valid, false, round, st);
-  }
-}
+// ------------------------------------------------------------------ frontier lists
+struct Frontier {
+  const int32_t* list;
+  int32_t n[kClasses];
+  int32_t b[kClasses];
+};
 
-// Workgroup id -> logical id such that consecutive logical ids (consecutive
-// vertex ranges in the dense sweep) land on the same XCD (workgroups are
-// dispatched round-robin over the 8 XCDs).
-__device__ __forceinline__ int32_t xcd_logical_block(int32_t b, int32_t G) {
-  constexpr int X = 8;
-  if (G % X != 0) return b;
-  return (b % X) * (G / X) + b / X;
-}
-
-// Dense round: active vertices found from the stamps (FIRST: every vertex of degree >= 2).
-template <int BLOCK, bool FIRST, typename Off>
-__device__ __forceinline__ void sweep_dense(const Args<Off>& a, const Sink& s, int32_t round, LaneStats& st,
-                                            int32_t* red, int32_t* sh_u, unsigned long long* sh_mask) {
+// The lists of round `round`: first round = the static lists; a round whose
+// appends overflowed = the compaction output; otherwise the appended lists.
+template <bool FIRST, typename Off>
+__device__ __forceinline__ Frontier frontier_of(const Args<Off>& a, int32_t round, bool& dense) {
   const Ctl* ctl = a.ctl;
-  const int32_t pop1 = ctl->pop[1], pop2 = ctl->pop[2];
-  const int32_t G = gridDim.x;
+  Frontier f;
+  region_bases(ctl, f.b);
+  dense = FIRST || ctl->overflow[round % 3][0] != 0;
+  const int32_t* cn = FIRST ? ctl->seed_fill : (dense ? ctl->ccnt[round & 1] : ctl->cnt[round % 3]);
+#pragma unroll
+  for (int k = 0; k < kClasses; ++k) f.n[k] = cn[k];
+  f.list = FIRST ? a.slist : list_of(a, round);
+  return f;
+}
+
+// Classes 0..2 of a frontier, shared among `workers` workgroups.
+template <int BLOCK, bool BATCH, typename Off>
+__device__ __forceinline__ void sweep_small(const Args<Off>& a, const Sink& s, const Frontier& f, bool dense,
+                                            int32_t round, int32_t worker, int32_t workers, LaneStats& st) {
+  constexpr int NW = BLOCK / kWave;
   const int lane = lane_id();
-  // workgroup class: static list, 64 entries per group examined by wavefront 0
-  {
-    const int32_t* S2 = a.slist + pop1;
-    const int32_t groups = (pop2 + (int32_t)G * kWave - 1) / ((int32_t)G * kWave);
-    for (int32_t g = 0; g < groups; ++g) {
-      if (threadIdx.x < kWave) {
-        const int32_t i = (int32_t)blockIdx.x + G * (g * kWave + lane);
-        bool act = false;
-        int32_t u = 0;
-        if (i < pop2) {
-          u = S2[i];
-          act = FIRST || a.stamp[u] == round;
-        }
-        const uint64_t m = ballot(act);
-        sh_u[lane] = u;
-        if (lane == 0) *sh_mask = m;
-      }
-      __syncthreads();
-      uint64_t m = *sh_mask;
-      __syncthreads();
-      while (m) {
-        const int b = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        upd_big<BLOCK>(a, s, sh_u[b], FIRST, round, st, red);
-      }
-      __syncthreads();
-    }
+  const int32_t gw = worker * NW + threadIdx.x / kWave;
+  // class 2: one wavefront per vertex
+  for (int32_t i = gw; i < f.n[2]; i += workers * NW) upd_wave<BATCH>(a, s, f.list[f.b[2] + i], dense, round, st);
+  // class 1: four 16-lane groups per wavefront
+  constexpr int GPW = kWave / kGroupLanes;
+  for (int32_t i0 = gw * GPW; i0 < f.n[1]; i0 += workers * NW * GPW) {
+    const int32_t i = i0 + lane / kGroupLanes;
+    const bool valid = i < f.n[1];
+    upd_group<BATCH>(a, s, valid ? f.list[f.b[1] + i] : 0, valid, dense, round, st);
   }
-  // wavefront class: static list, 64 consecutive entries per wavefront
-  {
-    constexpr int NW = BLOCK / kWave;
-    const int32_t* S1 = a.slist;
-    const int32_t gw = blockIdx.x * NW + threadIdx.x / kWave;
-    for (int32_t i0 = gw * kWave; i0 < pop1; i0 += G * NW * kWave) {
-      const int32_t i = i0 + lane;
-      int32_t u = 0;
-      bool act = false;
-      if (i < pop1) {
-        u = S1[i];
-        act = FIRST || a.stamp[u] == round;
-      }
-      uint64_t m = ballot(act);
-      while (m) {
-        const int b = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        upd_wave(a, s, __shfl(u, b), FIRST, round, st);
-      }
-    }
-  }
-  // lane class: sweep of the vertex range of this workgroup
-  {
-    const int32_t lb = xcd_logical_block(blockIdx.x, G);
-    const int64_t chunk = ((a.n + G - 1) / G + BLOCK - 1) / BLOCK * BLOCK;
-    const int64_t v_end = min(a.n, (lb + 1) * chunk);
-    for (int64_t v0 = lb * chunk; v0 < v_end; v0 += BLOCK) {
-      const int64_t v = v0 + threadIdx.x;
-      bool valid = false;
-      if (v < v_end) {
-        if (FIRST) {
-          valid = a.cls[v] == 0;
-        } else if (a.stamp[v] == round) {
-          valid = a.cls[v] == 0;
-        }
-      }
-      upd_lane(a, s, (int32_t)v, valid, FIRST, round, st);
-    }
+  // class 0: one lane per vertex
+  for (int32_t i = worker * BLOCK + threadIdx.x; i - lane < f.n[0]; i += workers * BLOCK) {
+    const bool valid = i < f.n[0];
+    upd_lane<BATCH>(a, s, valid ? f.list[f.b[0] + i] : 0, valid, dense, round, st);
   }
 }
 
@@ -630,12 +862,12 @@ __device__ __forceinline__ void sweep_dense(const Args<Off>& a, const Sink& s, i
 // One workgroup runs the remaining rounds on uncapped lists.  Within the
 // workgroup, stores become visible to all its wavefronts at each barrier, so no
 // launch is needed per round.
-template <int BLOCK, typename Off>
-__device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, LaneStats& st, int32_t* red) {
+template <int BLOCK, bool BATCH, typename Off>
+__device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, const Frontier& f0, LaneStats& st,
+                                         int32_t* red) {
   Ctl* ctl = a.ctl;
   const int tid = threadIdx.x;
-  const int32_t p0 = ctl->pop[0], p1 = ctl->pop[1];
-  if (tid < 4) {
+  if (tid < kClasses) {
     ctl->tail_cnt[0][tid] = 0;
     ctl->tail_cnt[1][tid] = 0;
   }
@@ -643,17 +875,22 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, Lane
   int32_t t = 0;
   for (;; ++t) {
     const int32_t r = round + t;
-    const int32_t* cc = (t == 0) ? ctl->cnt[round % 3] : ctl->tail_cnt[t & 1];
-    const int32_t n0 = ld_counter(cc + 0), n1 = ld_counter(cc + 1), n2 = ld_counter(cc + 2);
-    if (n0 + n1 + n2 == 0) break;
+    Frontier f = f0;
+    if (t > 0) {
+      f.list = list_of(a, r);
+#pragma unroll
+      for (int k = 0; k < kClasses; ++k) f.n[k] = ld_counter(&ctl->tail_cnt[t & 1][k]);
+    }
+    if (f.n[0] + f.n[1] + f.n[2] + f.n[3] == 0) break;
     if (t >= kTailRoundCap) {
       if (tid == 0) ctl->error = 1;
       break;
     }
     const Sink s = make_sink(a, r + 1, ctl->tail_cnt[(t + 1) & 1], nullptr, false);
-    sweep_lists<BLOCK>(a, s, list_of(a, r), n0, n1, n2, r, p0, p0 + p1, 0, 1, st, red);
+    for (int32_t i = 0; i < f.n[3]; ++i) upd_big_lite<BLOCK, BATCH>(a, s, f.list[f.b[3] + i], r, st, red);
+    sweep_small<BLOCK, BATCH>(a, s, f, false, r, 0, 1, st);
     __syncthreads();
-    if (t > 0 && tid < 4) ctl->tail_cnt[t & 1][tid] = 0;  // reused by round t+2
+    if (t > 0 && tid < kClasses) ctl->tail_cnt[t & 1][tid] = 0;  // reused by round t+2
     __syncthreads();
   }
   if (tid < 4) {
@@ -671,111 +908,150 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, Lane
 // ------------------------------------------------------------------ kernels
 // est = degree, degree class, class populations (one atomic per workgroup and class).
 template <typename Off>
-__global__ __launch_bounds__(256) void k_init(Args<Off> a) {
-  __shared__ uint32_t part[3][256 / kWave];
+__global__ __launch_bounds__(256) void k_init(Args<Off> a, int32_t r0, int32_t t0, int32_t t1, int32_t t2) {
+  __shared__ uint32_t part[kClasses][256 / kWave];
+  // the round after the first (all-vertices) round rebuilds its lists by compaction: no appends in the first round
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->overflow[(r0 + 1) % 3][0] = 1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  uint32_t p[3] = {0, 0, 0};
+  uint32_t p[kClasses] = {0, 0, 0, 0};
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
     const int32_t d = (int32_t)(a.row_ptr[v + 1] - a.row_ptr[v]);
     a.est[v] = d;
     a.plen[v] = 0;
-    const uint8_t c = d <= a.t1 ? 0 : (d <= a.t2 ? 1 : 2);
+    const uint8_t c = d <= t0 ? 0 : (d <= t1 ? 1 : (d <= t2 ? 2 : 3));
     a.cls[v] = c;
-    p[c] += 1;
+#pragma unroll
+    for (int k = 0; k < kClasses; ++k) p[k] += c == k;
   }
   const int wave = threadIdx.x / kWave;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < kClasses; ++k) {
     const uint32_t w = wave_sum(p[k]);
     if (lane_id() == 0) part[k][wave] = w;
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (threadIdx.x < kClasses) {
     uint32_t t = 0;
     for (int w = 0; w < 256 / kWave; ++w) t += part[threadIdx.x][w];
     if (t) atomicAdd(&a.ctl->pop[threadIdx.x], (int32_t)t);
   }
 }
 
-// Static lists of the wavefront and workgroup classes.  Each workgroup owns a
-// contiguous vertex range: a counting pass, one atomic per class, a writing pass.
-template <typename Off>
-__global__ __launch_bounds__(256) void k_seed(Args<Off> a) {
-  int32_t* fill = a.ctl->seed_fill;
-  constexpr int BLOCK = 256;
-  __shared__ int32_t red[BLOCK / kWave];
-  __shared__ int32_t base_sh[3];
-  const int64_t chunk = (a.n + gridDim.x - 1) / gridDim.x;
-  const int64_t v0 = (int64_t)blockIdx.x * chunk, v1 = min(a.n, v0 + chunk);
-  int32_t mine[3] = {0, 0, 0};
-  for (int64_t v = v0 + threadIdx.x; v < v1; v += BLOCK) {
-    const int c = a.cls[v];
-    mine[1] += c == 1;
-    mine[2] += c == 2;
+// Build class lists from a per-vertex predicate: SEED = the first-round lists
+// (every vertex of degree >= 2, into slist / seed_fill), otherwise the lists of
+// a round whose appends overflowed (stamp == round, into ccnt).  Each workgroup
+// owns a contiguous vertex range split among its wavefronts: a counting pass,
+// one atomic per workgroup and class, a writing pass without barriers.
+template <bool SEED, typename Off>
+__global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t round) {
+  constexpr int BLOCK = 256, NW = BLOCK / kWave;
+  __shared__ int32_t wcnt[NW][kClasses];
+  __shared__ int32_t bbase[kClasses];
+  Ctl* ctl = a.ctl;
+  if (!SEED && ctl->overflow[round % 3][0] == 0) return;
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  const int64_t chunk = ((a.n + gridDim.x - 1) / gridDim.x + kWave * NW - 1) / (kWave * NW) * (kWave * NW);
+  const int64_t wchunk = chunk / NW;
+  const int64_t w0 = (int64_t)blockIdx.x * chunk + wave * wchunk, w1 = min(a.n, w0 + wchunk);
+  auto cls_if_active = [&](int64_t v) -> int {
+    if (v >= w1) return kClasses;
+    const bool act = SEED ? a.est[v] >= 2 : a.stamp[v] == round;
+    return act ? (int)a.cls[v] : kClasses;
+  };
+  int32_t mine[kClasses] = {0, 0, 0, 0};
+  for (int64_t vb = w0; vb < w1; vb += kWave) {
+    const int c = cls_if_active(vb + lane);
+#pragma unroll
+    for (int k = 0; k < kClasses; ++k) mine[k] += c == k;
   }
-  const int32_t pop1 = a.ctl->pop[1];
-  for (int k = 1; k < 3; ++k) {
-    int32_t total = 0;
-    (void)block_excl_scan<BLOCK>(mine[k], total, red);
-    if (threadIdx.x == 0) base_sh[k] = total ? atomicAdd(&fill[k], total) : 0;
+#pragma unroll
+  for (int k = 0; k < kClasses; ++k) {
+    const int32_t w = wave_sum(mine[k]);
+    if (lane == 0) wcnt[wave][k] = w;
   }
   __syncthreads();
-  int32_t run[3] = {0, base_sh[1], base_sh[2]};
-  for (int64_t vb = v0; vb < v1; vb += BLOCK) {
-    const int64_t v = vb + threadIdx.x;
-    const int c = v < v1 ? a.cls[v] : 0;
-    for (int k = 1; k < 3; ++k) {
-      int32_t total = 0;
-      const int32_t off = block_excl_scan<BLOCK>(c == k ? 1 : 0, total, red);
-      if (c == k) a.slist[(k == 2 ? pop1 : 0) + run[k] + off] = (int32_t)v;
-      run[k] += total;
+  if (threadIdx.x < kClasses) {
+    int32_t t = 0;
+    for (int w = 0; w < NW; ++w) t += wcnt[w][threadIdx.x];
+    int32_t* fill = SEED ? ctl->seed_fill : ctl->ccnt[round & 1];
+    bbase[threadIdx.x] = t ? atomicAdd(&fill[threadIdx.x], t) : 0;
+  }
+  __syncthreads();
+  int32_t rb[kClasses];
+  region_bases(ctl, rb);
+  int32_t pos[kClasses];
+#pragma unroll
+  for (int k = 0; k < kClasses; ++k) {
+    int32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wcnt[w][k];
+    pos[k] = rb[k] + bbase[k] + before;
+  }
+  int32_t* out = SEED ? a.slist : list_of(a, round);
+  for (int64_t vb = w0; vb < w1; vb += kWave) {
+    const int64_t v = vb + lane;
+    const int c = cls_if_active(v);
+#pragma unroll
+    for (int k = 0; k < kClasses; ++k) {
+      const uint64_t m = ballot(c == k);
+      if (c == k) out[pos[k] + lanes_below(m)] = (int32_t)v;
+      pos[k] += popc(m);
     }
   }
 }
 
-// One round (round number `round`).  FIRST: the dense first round over every
-// vertex of degree >= 2.  Otherwise the round runs densely from the stamps when
-// its sparse lists overflowed, else from the lists; a small list frontier is
-// handed to the single-workgroup tail.
-template <int BLOCK, bool FIRST, typename Off>
+// One round, classes 0..2 (round number `round`).  A small frontier without
+// class-3 vertices is handed to the single-workgroup tail.
+template <int BLOCK, bool FIRST, bool BATCH, typename Off>
 __global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t round, int32_t collect_stats) {
-  __shared__ int32_t red[kHugeThresholds * (BLOCK / kWave)];
   __shared__ unsigned long long red64[kLaneStats * (BLOCK / kWave)];
-  __shared__ int32_t sh_u[kWave];
-  __shared__ unsigned long long sh_mask;
+  __shared__ int32_t red[kKary * (BLOCK / kWave)];
   Ctl* ctl = a.ctl;
-  const int slot = round % 3;
-  const bool dense = FIRST || ctl->overflow[slot][0] != 0;
-  const int32_t n0 = ctl->cnt[slot][0], n1 = ctl->cnt[slot][1], n2 = ctl->cnt[slot][2];
+  bool dense = false;
+  const Frontier f = frontier_of<FIRST>(a, round, dense);
   if (blockIdx.x == 0 && threadIdx.x < 4) {
     ctl->cnt[(round + 2) % 3][threadIdx.x] = 0;
     ctl->overflow[(round + 2) % 3][threadIdx.x] = 0;
+    ctl->ccnt[(round + 1) & 1][threadIdx.x] = 0;  // compaction output of the next round
   }
   LaneStats st;
-  if (!dense) {
-    const int32_t tot = n0 + n1 + n2;
-    if (tot == 0) return;
-    if (tot <= a.tail_threshold) {
-      if (blockIdx.x == 0) {
-        run_tail<BLOCK>(a, round, st, red);
-        if (collect_stats) flush_stats<BLOCK>(ctl, st, red64);
-      }
-      return;
+  const int32_t tot = f.n[0] + f.n[1] + f.n[2] + f.n[3];
+  if (!FIRST && tot == 0) return;
+  if (!FIRST && !dense && f.n[3] == 0 && (int64_t)f.n[0] + 4ll * f.n[1] + 16ll * f.n[2] <= a.tail_threshold) {
+    if (blockIdx.x == 0) {
+      run_tail<BLOCK, BATCH>(a, round, f, st, red);
+      if (collect_stats) flush_stats<BLOCK>(ctl, st, red64);
     }
+    return;
   }
   const int nslot = (round + 1) % 3;
   const Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
-  if (dense) {
-    sweep_dense<BLOCK, FIRST>(a, s, round, st, red, sh_u, &sh_mask);
-  } else {
-    const int32_t p0 = ctl->pop[0], p1 = ctl->pop[1];
-    sweep_lists<BLOCK>(a, s, list_of(a, round), n0, n1, n2, round, p0, p0 + p1, blockIdx.x, gridDim.x, st, red);
-  }
+  sweep_small<BLOCK, BATCH>(a, s, f, FIRST, round, blockIdx.x, gridDim.x, st);
   if (collect_stats) flush_stats<BLOCK>(ctl, st, red64);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     atomicAdd(&ctl->stats[ST_ROUNDS], 1ull);
     if (dense) atomicAdd(&ctl->stats[ST_DENSE_ROUNDS], 1ull);
   }
+}
+
+// One round, class 3 (degree above the wavefront class): one workgroup per
+// vertex.  Runs before k_round of the same round; a round handed to the tail
+// has no class-3 vertex, so this kernel then finds nothing to do.
+template <bool FIRST, bool BATCH, typename Off>
+__global__ __launch_bounds__(kBigBlock) void k_big(Args<Off> a, int32_t round, int32_t collect_stats) {
+  constexpr int BLOCK = kBigBlock;
+  __shared__ int32_t hist[kHistBins];
+  __shared__ int32_t red[kKary * (BLOCK / kWave)];
+  __shared__ unsigned long long red64[kLaneStats * (BLOCK / kWave)];
+  Ctl* ctl = a.ctl;
+  bool dense = false;
+  const Frontier f = frontier_of<FIRST>(a, round, dense);
+  if (f.n[3] == 0) return;
+  LaneStats st;
+  const int nslot = (round + 1) % 3;
+  const Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
+  for (int32_t i = blockIdx.x; i < f.n[3]; i += gridDim.x)
+    upd_big<BLOCK, BATCH>(a, s, f.list[f.b[3] + i], FIRST, round, st, red, hist);
+  if (collect_stats) flush_stats<BLOCK>(ctl, st, red64);
 }
 
 // Precondition check (only when requested): ids in range, no self-loops,

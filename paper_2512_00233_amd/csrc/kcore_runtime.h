@@ -9,11 +9,12 @@ namespace kcore {
 
 // Resolved launch parameters (library defaults overridden by kcore_tuning).
 struct Tuning {
-  int t1;         // lane class: degree <= t1
-  int t2;         // wavefront class: degree <= t2
-  int t3;         // workgroup keeps values in registers up to t3 neighbours
-  int tail;       // frontier size that hands the run to one workgroup
-  int grid;       // workgroups per round launch
+  int t0;         // class 0 (one lane): degree <= t0
+  int t1;         // class 1 (16-lane group): degree <= t1
+  int t2;         // class 2 (wavefront): degree <= t2; above: class 3 (workgroup)
+  int tail;       // frontier work that hands the run to one workgroup
+  int grid;       // workgroups per small-class round launch
+  int big_grid;   // workgroups per class-3 round launch
   int poll;       // rounds in the first chunk between host checks
   int one_sided;  // activation rule
   int timing;     // HIP events around every round launch

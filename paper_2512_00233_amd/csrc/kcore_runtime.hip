@@ -1,6 +1,6 @@
 // Host runtime and C ABI of libkcore: workspace per device, the round driver
-// (dense first round, sparse rounds enqueued in chunks, convergence polled on a
-// pinned copy of the device control block) and argument checking.
+// (first round over every vertex, later rounds enqueued in chunks, convergence
+// polled on a pinned copy of the device control block) and argument checking.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,12 +46,13 @@ struct Workspace {
   int32_t* slist = nullptr;
   int32_t* plen = nullptr;
   int32_t* plow = nullptr;
+  int32_t* vbase = nullptr;
   int32_t* pruned = nullptr;
-  int64_t* host_nnz = nullptr;  // pinned
   Ctl* ctl = nullptr;
-  Ctl* host_ctl = nullptr;   // pinned
-  int32_t* verr = nullptr;   // validation result (device)
-  int32_t* host_verr = nullptr;
+  Ctl* host_ctl = nullptr;      // pinned
+  int32_t* verr = nullptr;      // validation result (device)
+  int32_t* host_verr = nullptr;  // pinned
+  int64_t* host_nnz = nullptr;   // pinned
   int32_t epoch = 1;
   std::vector<hipEvent_t> events;  // timing mode: one pair per round launch
   std::mutex mu;
@@ -67,12 +68,12 @@ struct Workspace {
 
   void release() {
     for (void* p : {(void*)stamp, (void*)cls, (void*)lists[0], (void*)lists[1], (void*)slist, (void*)plen,
-                    (void*)plow, (void*)pruned})
+                    (void*)plow, (void*)vbase, (void*)pruned})
       (void)hipFree(p);
     stamp = nullptr;
     cls = nullptr;
     lists[0] = lists[1] = nullptr;
-    slist = plen = plow = pruned = nullptr;
+    slist = plen = plow = vbase = pruned = nullptr;
     cap_n = 0;
     cap_nnz = 0;
   }
@@ -103,11 +104,13 @@ static kcore_status get_workspace(Workspace** out) {
   return KCORE_OK;
 }
 
-static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, hipStream_t st) {
-  if (n <= ws->cap_n && nnz <= ws->cap_nnz) return KCORE_OK;
+static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, bool batched, hipStream_t st) {
+  const bool need_vbase = batched && !ws->vbase;
+  if (n <= ws->cap_n && nnz <= ws->cap_nnz && !need_vbase) return KCORE_OK;
   KC_HIP(hipStreamSynchronize(st));
   const int64_t cap = std::max<int64_t>({n, ws->cap_n, 1024});
   const int64_t cap_e = std::max<int64_t>({nnz, ws->cap_nnz, 1024});
+  const bool keep_vbase = batched || ws->vbase;
   ws->release();
   bool ok = hipMalloc(&ws->stamp, sizeof(int32_t) * cap) == hipSuccess &&
             hipMalloc(&ws->cls, sizeof(uint8_t) * cap) == hipSuccess &&
@@ -116,6 +119,7 @@ static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, hipSt
             hipMalloc(&ws->slist, sizeof(int32_t) * cap) == hipSuccess &&
             hipMalloc(&ws->plen, sizeof(int32_t) * cap) == hipSuccess &&
             hipMalloc(&ws->plow, sizeof(int32_t) * cap) == hipSuccess &&
+            (!keep_vbase || hipMalloc(&ws->vbase, sizeof(int32_t) * cap) == hipSuccess) &&
             hipMalloc(&ws->pruned, sizeof(int32_t) * cap_e) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
@@ -133,11 +137,12 @@ static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, hipSt
 // ------------------------------------------------------------------ tuning
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   Tuning r;
-  r.t1 = kThreadMaxDeg;
-  r.t2 = kWave * kWaveRegs;
-  r.t3 = 256 * kBlockRegs;
+  r.t0 = kLaneMaxDeg;
+  r.t1 = kGroupMaxDeg;
+  r.t2 = kWaveMaxDeg;
   r.tail = 2048;
   r.grid = 8 * num_cus;
+  r.big_grid = 4 * num_cus;
   r.poll = 4;
   r.one_sided = 0;
   r.timing = 0;
@@ -145,31 +150,182 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.prune = 1;
   if (const char* e = std::getenv("KCORE_TAIL")) r.tail = std::atoi(e);
   if (t) {
-    if (t->thread_max_deg > 0) r.t1 = std::min(t->thread_max_deg, kThreadMaxDeg);
-    if (t->wave_max_deg > 0) r.t2 = std::min(t->wave_max_deg, kWave * kWaveRegs);
-    if (t->block_max_deg > 0) r.t3 = std::min(t->block_max_deg, 256 * kBlockRegs);
+    if (t->thread_max_deg > 0) r.t0 = std::min(t->thread_max_deg, kLaneMaxDeg);
+    if (t->group_max_deg > 0) r.t1 = std::min(t->group_max_deg, kGroupMaxDeg);
+    if (t->wave_max_deg > 0) r.t2 = std::min(t->wave_max_deg, kWaveMaxDeg);
     if (t->tail_threshold > 0) r.tail = t->tail_threshold;
     else if (t->tail_threshold < 0) r.tail = 0;  // tail disabled
     if (t->grid_blocks > 0) r.grid = t->grid_blocks;
+    if (t->big_grid_blocks > 0) r.big_grid = t->big_grid_blocks;
     if (t->rounds_per_poll > 0) r.poll = t->rounds_per_poll;
     r.one_sided = t->activation == 1;
     r.timing = t->timing == 1;
     if (t->list_cap > 0) r.list_cap = t->list_cap;
     r.prune = t->no_prune != 1;
   }
-  r.t1 = std::max(r.t1, 1);
+  r.t0 = std::max(r.t0, 1);
+  r.t1 = std::max(r.t1, r.t0);
   r.t2 = std::max(r.t2, r.t1);
   r.grid = std::max(8, (r.grid + 7) / 8 * 8);
+  r.big_grid = std::max(1, r.big_grid);
   return r;
 }
 
-static bool env_validate() {
-  const char* e = std::getenv("KCORE_VALIDATE");
+static bool env_flag(const char* name) {
+  const char* e = std::getenv(name);
   return e && e[0] == '1';
 }
 
 // ------------------------------------------------------------------ driver
 constexpr int kBlock = 256;
+
+// Every vertex of every graph (one graph: vbase unused) to its fixpoint.
+// row_ptr holds global edge offsets; with BATCH, col holds graph-local ids.
+template <bool BATCH, typename Off>
+static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off* row_ptr, const int32_t* col,
+                               int32_t* out, const Tuning& tu, kcore_stats* stats, hipStream_t st) {
+  const int init_grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
+  const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, (int64_t)ws->num_cus * 8));
+  if (ws->epoch > (1 << 29)) {
+    KC_HIP(hipMemsetAsync(ws->stamp, 0, sizeof(int32_t) * ws->cap_n, st));
+    ws->epoch = 1;
+  }
+  Args<Off> a;
+  a.n = n;
+  a.row_ptr = row_ptr;
+  a.col = col;
+  a.vbase = BATCH ? ws->vbase : nullptr;
+  a.est = out;
+  a.stamp = ws->stamp;
+  a.cls = ws->cls;
+  a.lists[0] = ws->lists[0];
+  a.lists[1] = ws->lists[1];
+  a.slist = ws->slist;
+  a.pruned = ws->pruned;
+  a.plen = ws->plen;
+  a.plow = ws->plow;
+  a.ctl = ws->ctl;
+  a.tail_threshold = tu.tail;
+  a.list_cap = tu.list_cap;
+  a.one_sided = tu.one_sided;
+  a.prune = tu.prune;
+  const int32_t collect = stats ? 1 : 0;
+  const bool trace = env_flag("KCORE_TRACE");
+  const bool timing = tu.timing || trace;
+  const int32_t r0 = ws->epoch;
+  double first_ms = 0, later_ms = 0;
+  unsigned long long first_st[4] = {0, 0, 0, 0};
+  if (timing) {
+    kcore_status s = ws->need_events(2 * 64);
+    if (s != KCORE_OK) return s;
+  }
+  KC_HIP(hipMemsetAsync(ws->ctl, 0, sizeof(Ctl), st));
+  hipLaunchKernelGGL(k_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, r0, tu.t0, tu.t1, tu.t2);
+  hipLaunchKernelGGL((k_compact<true, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, r0);
+  if (timing) KC_HIP(hipEventRecord(ws->events[0], st));
+  hipLaunchKernelGGL((k_big<true, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, r0, collect);
+  hipLaunchKernelGGL((k_round<kBlock, true, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, r0, collect);
+  KC_HIP(hipGetLastError());
+  unsigned long long prev_st[16];
+  if (timing) {
+    KC_HIP(hipEventRecord(ws->events[1], st));
+    KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    KC_HIP(hipStreamSynchronize(st));
+    float ms = 0;
+    KC_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
+    first_ms = ms;
+    for (int q = 0; q < 4; ++q) first_st[q] = ws->host_ctl->stats[ST_UPDATES + q];
+    std::memcpy(prev_st, ws->host_ctl->stats, sizeof(prev_st));
+    if (trace) {
+      const Ctl& h = *ws->host_ctl;
+      std::fprintf(stderr, "[kcore-trace] n=%lld nnz=%lld pop=%d/%d/%d/%d first visits=%llu updates=%llu "
+                   "changes=%llu acts=%llu ms=%.3f\n", (long long)n, (long long)nnz, h.pop[0], h.pop[1], h.pop[2],
+                   h.pop[3], prev_st[ST_VISITS], prev_st[ST_UPDATES], prev_st[ST_CHANGES], prev_st[ST_ACTIVATIONS],
+                   first_ms);
+    }
+  }
+  int64_t launches = 1;
+  int32_t r = r0 + 1;
+  int K = trace ? 1 : tu.poll;
+  for (;;) {
+    for (int i = 0; i < K; ++i) {
+      if (timing) KC_HIP(hipEventRecord(ws->events[2 * i], st));
+      hipLaunchKernelGGL((k_compact<false, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, r + i);
+      hipLaunchKernelGGL((k_big<false, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, r + i, collect);
+      hipLaunchKernelGGL((k_round<kBlock, false, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, r + i,
+                         collect);
+      if (timing) KC_HIP(hipEventRecord(ws->events[2 * i + 1], st));
+    }
+    KC_HIP(hipGetLastError());
+    launches += K;
+    r += K;
+    KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    KC_HIP(hipStreamSynchronize(st));
+    const Ctl& h = *ws->host_ctl;
+    if (timing) {
+      for (int i = 0; i < K; ++i) {
+        float ms = 0;
+        KC_HIP(hipEventElapsedTime(&ms, ws->events[2 * i], ws->events[2 * i + 1]));
+        later_ms += ms;
+        if (trace) {
+          std::fprintf(stderr, "[kcore-trace] round=%d front=%d/%d/%d/%d dense=%d visits=%llu updates=%llu "
+                       "changes=%llu acts=%llu full=%llu pw=%llu tail=%llu ms=%.3f\n", r - 1 - r0,
+                       h.cnt[r % 3][0], h.cnt[r % 3][1], h.cnt[r % 3][2], h.cnt[r % 3][3], h.overflow[r % 3][0],
+                       h.stats[ST_VISITS] - prev_st[ST_VISITS], h.stats[ST_UPDATES] - prev_st[ST_UPDATES],
+                       h.stats[ST_CHANGES] - prev_st[ST_CHANGES], h.stats[ST_ACTIVATIONS] - prev_st[ST_ACTIVATIONS],
+                       h.stats[ST_FULL_SCANS] - prev_st[ST_FULL_SCANS],
+                       h.stats[ST_PRUNE_WRITES] - prev_st[ST_PRUNE_WRITES],
+                       h.stats[ST_TAIL_ROUNDS] - prev_st[ST_TAIL_ROUNDS], ms);
+          std::memcpy(prev_st, h.stats, sizeof(prev_st));
+        }
+      }
+    }
+    const int32_t* c = h.cnt[r % 3];
+    if (h.overflow[r % 3][0] == 0 && c[0] == 0 && c[1] == 0 && c[2] == 0 && c[3] == 0) break;
+    if ((int64_t)r - r0 > (int64_t)1 << 24) return fail(KCORE_E_HIP, "round limit exceeded");
+    K = trace ? 1 : std::min(2 * K, 64);
+  }
+  const Ctl& hc = *ws->host_ctl;
+  if (hc.error) return fail(KCORE_E_HIP, "tail round cap reached (internal error)");
+  ws->epoch = r + (int32_t)hc.stats[ST_TAIL_ROUNDS] + 4;
+  if (stats) {
+    stats->rounds = (int64_t)hc.stats[ST_ROUNDS];
+    stats->tail_rounds = (int64_t)hc.stats[ST_TAIL_ROUNDS];
+    stats->launches = launches;
+    stats->vertex_updates = (int64_t)hc.stats[ST_UPDATES];
+    stats->edge_visits = (int64_t)hc.stats[ST_VISITS];
+    stats->changes = (int64_t)hc.stats[ST_CHANGES];
+    stats->activations = (int64_t)hc.stats[ST_ACTIVATIONS];
+    stats->dense_vertex_updates = (int64_t)first_st[0];
+    stats->dense_edge_visits = (int64_t)first_st[1];
+    stats->dense_changes = (int64_t)first_st[2];
+    stats->dense_activations = (int64_t)first_st[3];
+    stats->dense_ms = first_ms;
+    stats->sparse_ms = later_ms;
+    stats->full_scans = (int64_t)hc.stats[ST_FULL_SCANS];
+    stats->prune_writes = (int64_t)hc.stats[ST_PRUNE_WRITES];
+    stats->dense_rounds = (int64_t)hc.stats[ST_DENSE_ROUNDS];
+  }
+  return KCORE_OK;
+}
+
+template <typename Off>
+static kcore_status validate_csr(Workspace* ws, int64_t n, const Off* row_ptr, const int32_t* col,
+                                 hipStream_t st) {
+  const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
+  KC_HIP(hipMemsetAsync(ws->verr, 0x7f, sizeof(int32_t), st));
+  hipLaunchKernelGGL(k_validate<Off>, dim3(grid), dim3(kBlock), 0, st, n, row_ptr, col, ws->verr);
+  KC_HIP(hipGetLastError());
+  KC_HIP(hipMemcpyAsync(ws->host_verr, ws->verr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  KC_HIP(hipStreamSynchronize(st));
+  const int32_t code = *ws->host_verr;
+  if (code != 0x7f7f7f7f) {
+    static const char* what[] = {"", "neighbour id out of range", "self-loop", "row not strictly increasing",
+                                 "graph not symmetric"};
+    return fail(KCORE_E_INVALID, std::string("KCORE_VALIDATE: ") + what[std::min(code, 4)]);
+  }
+  return KCORE_OK;
+}
 
 template <typename Off>
 static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t* col, int32_t* out,
@@ -187,123 +343,14 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
   KC_HIP(hipStreamSynchronize(st));
   const int64_t nnz = sizeof(Off) == 8 ? *ws->host_nnz : (int64_t)*(const int32_t*)ws->host_nnz;
   if (nnz < 0) return fail(KCORE_E_INVALID, "row_ptr[n] is negative");
-  s = ensure_capacity(ws, n, nnz, st);
+  s = ensure_capacity(ws, n, nnz, false, st);
   if (s != KCORE_OK) return s;
-  const Tuning tu = resolve_tuning(tuning, ws->num_cus);
-  const int init_grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
-
-  if (env_validate()) {
-    KC_HIP(hipMemsetAsync(ws->verr, 0x7f, sizeof(int32_t), st));
-    hipLaunchKernelGGL(k_validate<Off>, dim3(init_grid), dim3(kBlock), 0, st, n, row_ptr, col, ws->verr);
-    KC_HIP(hipGetLastError());
-    KC_HIP(hipMemcpyAsync(ws->host_verr, ws->verr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    KC_HIP(hipStreamSynchronize(st));
-    int32_t code = *ws->host_verr;
-    if (code != 0x7f7f7f7f) {
-      static const char* what[] = {"", "neighbour id out of range", "self-loop", "row not strictly increasing",
-                                   "graph not symmetric"};
-      return fail(KCORE_E_INVALID, std::string("KCORE_VALIDATE: ") + what[std::min(code, 4)]);
-    }
-  }
-
-  if (ws->epoch > (1 << 29)) {
-    KC_HIP(hipMemsetAsync(ws->stamp, 0, sizeof(int32_t) * ws->cap_n, st));
-    ws->epoch = 1;
-  }
-  Args<Off> a;
-  a.n = n;
-  a.row_ptr = row_ptr;
-  a.col = col;
-  a.est = out;
-  a.stamp = ws->stamp;
-  a.cls = ws->cls;
-  a.lists[0] = ws->lists[0];
-  a.lists[1] = ws->lists[1];
-  a.slist = ws->slist;
-  a.pruned = ws->pruned;
-  a.plen = ws->plen;
-  a.plow = ws->plow;
-  a.ctl = ws->ctl;
-  a.t1 = tu.t1;
-  a.t2 = tu.t2;
-  a.t3 = tu.t3;
-  a.tail_threshold = tu.tail;
-  a.one_sided = tu.one_sided;
-  a.list_cap = tu.list_cap;
-  a.prune = tu.prune;
-  const int32_t collect = stats ? 1 : 0;
-  const int seed_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 8191) / 8192, 1024));
-
-  const int32_t r0 = ws->epoch;
-  double dense_ms = 0, sparse_ms = 0;
-  unsigned long long dense_st[4] = {0, 0, 0, 0};
-  if (tu.timing) {
-    s = ws->need_events(2 * 64);
+  if (env_flag("KCORE_VALIDATE")) {
+    s = validate_csr<Off>(ws, n, row_ptr, col, st);
     if (s != KCORE_OK) return s;
   }
-  KC_HIP(hipMemsetAsync(ws->ctl, 0, sizeof(Ctl), st));
-  hipLaunchKernelGGL(k_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a);
-  hipLaunchKernelGGL(k_seed<Off>, dim3(seed_grid), dim3(kBlock), 0, st, a);
-  if (tu.timing) KC_HIP(hipEventRecord(ws->events[0], st));
-  hipLaunchKernelGGL((k_round<kBlock, true, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, r0, collect);
-  KC_HIP(hipGetLastError());
-  if (tu.timing) {
-    KC_HIP(hipEventRecord(ws->events[1], st));
-    KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    KC_HIP(hipStreamSynchronize(st));
-    float ms = 0;
-    KC_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
-    dense_ms = ms;
-    for (int q = 0; q < 4; ++q) dense_st[q] = ws->host_ctl->stats[ST_UPDATES + q];
-  }
-  int64_t launches = 1;
-  int32_t r = r0 + 1;
-  int K = tu.poll;
-  for (;;) {
-    for (int i = 0; i < K; ++i) {
-      if (tu.timing) KC_HIP(hipEventRecord(ws->events[2 * i], st));
-      hipLaunchKernelGGL((k_round<kBlock, false, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, r + i, collect);
-      if (tu.timing) KC_HIP(hipEventRecord(ws->events[2 * i + 1], st));
-    }
-    KC_HIP(hipGetLastError());
-    launches += K;
-    r += K;
-    KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    KC_HIP(hipStreamSynchronize(st));
-    if (tu.timing) {
-      for (int i = 0; i < K; ++i) {
-        float ms = 0;
-        KC_HIP(hipEventElapsedTime(&ms, ws->events[2 * i], ws->events[2 * i + 1]));
-        sparse_ms += ms;
-      }
-    }
-    const int32_t* c = ws->host_ctl->cnt[r % 3];
-    if (ws->host_ctl->overflow[r % 3][0] == 0 && c[0] == 0 && c[1] == 0 && c[2] == 0) break;
-    if ((int64_t)r - r0 > (int64_t)1 << 24) return fail(KCORE_E_HIP, "round limit exceeded");
-    K = std::min(2 * K, 64);
-  }
-  const Ctl& hc = *ws->host_ctl;
-  if (hc.error) return fail(KCORE_E_HIP, "tail round cap reached (internal error)");
-  ws->epoch = r + (int32_t)hc.stats[ST_TAIL_ROUNDS] + 4;
-  if (stats) {
-    stats->rounds = (int64_t)hc.stats[ST_ROUNDS];
-    stats->tail_rounds = (int64_t)hc.stats[ST_TAIL_ROUNDS];
-    stats->launches = launches;
-    stats->vertex_updates = (int64_t)hc.stats[ST_UPDATES];
-    stats->edge_visits = (int64_t)hc.stats[ST_VISITS];
-    stats->changes = (int64_t)hc.stats[ST_CHANGES];
-    stats->activations = (int64_t)hc.stats[ST_ACTIVATIONS];
-    stats->dense_vertex_updates = (int64_t)dense_st[0];
-    stats->dense_edge_visits = (int64_t)dense_st[1];
-    stats->dense_changes = (int64_t)dense_st[2];
-    stats->dense_activations = (int64_t)dense_st[3];
-    stats->dense_ms = dense_ms;
-    stats->sparse_ms = sparse_ms;
-    stats->full_scans = (int64_t)hc.stats[ST_FULL_SCANS];
-    stats->prune_writes = (int64_t)hc.stats[ST_PRUNE_WRITES];
-    stats->dense_rounds = (int64_t)hc.stats[ST_DENSE_ROUNDS];
-  }
-  return KCORE_OK;
+  const Tuning tu = resolve_tuning(tuning, ws->num_cus);
+  return run_rounds<false, Off>(ws, n, nnz, row_ptr, col, out, tu, stats, st);
 }
 
 }  // namespace kcore
@@ -329,7 +376,7 @@ kcore_status kcore_decompose_ex(int64_t n, const int64_t* row_ptr, const int32_t
 
 const char* kcore_last_error(void) { return g_last_error.c_str(); }
 
-const char* kcore_version(void) { return "kcore-mi355x 0.1.0 (gfx950)"; }
+const char* kcore_version(void) { return "kcore-mi355x 0.2.0 (gfx950)"; }
 
 kcore_status kcore_release_workspace(void) {
   int dev = 0;

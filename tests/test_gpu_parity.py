@@ -84,7 +84,7 @@ def test_star_with_a_million_leaves():
 
 @pytest.mark.parametrize("k", [200, 1500, 3000])
 def test_large_cliques(k):
-    # wavefront path (k-1 <= 512), workgroup register path (<= 2048), multi-pass path (> 2048)
+    # wavefront path (k-1 <= 512), workgroup register path (<= 2048), LDS histogram path (> 2048)
     n, edges = sg.complete(k)
     rp, ci = sg.to_csr(n, edges)
     assert (run_gpu(rp, ci) == k - 1).all()
@@ -155,12 +155,13 @@ TUNINGS = {
     "no_tail": dict(tail_threshold=-1),
     "tail_everything": dict(tail_threshold=1 << 30),
     "one_sided": dict(activation=1),
-    "tiny_grid": dict(grid_blocks=8),
-    "lane_only_small": dict(thread_max_deg=2, wave_max_deg=64, block_max_deg=256),
-    "all_huge": dict(thread_max_deg=1, wave_max_deg=1, block_max_deg=1),
+    "tiny_grid": dict(grid_blocks=8, big_grid_blocks=1),
+    "lane_only_small": dict(thread_max_deg=2, group_max_deg=16, wave_max_deg=64),
+    "all_workgroup": dict(thread_max_deg=1, group_max_deg=1, wave_max_deg=1),
+    "all_wavefront": dict(thread_max_deg=1, group_max_deg=1),
     "poll_every_round": dict(rounds_per_poll=1, timing=1),
-    "always_dense": dict(list_cap=1, tail_threshold=-1),
-    "always_sparse": dict(list_cap=1 << 30),
+    "always_compact": dict(list_cap=1, tail_threshold=-1),
+    "never_compact": dict(list_cap=1 << 30),
     "no_prune": dict(no_prune=1),
     "no_prune_one_sided": dict(no_prune=1, activation=1, list_cap=64),
 }
