@@ -63,7 +63,8 @@ typedef struct kcore_tuning {
   int32_t list_cap;        /* frontier list capacity per degree class; beyond it the next round rebuilds
                               its lists from the round stamps (0: library default 8192) */
   int32_t no_prune;        /* 1: disable the pruned adjacency (always scan the full neighbour list) */
-  int32_t reserved[5];
+  int32_t no_graph;        /* 1: launch every round directly instead of replaying captured hipGraphs */
+  int32_t reserved[4];
 } kcore_tuning;
 
 /* Per-call statistics (optional output).  Edge visits count the adjacency
@@ -116,6 +117,49 @@ kcore_status kcore_decompose32(int64_t n, const int32_t* row_ptr, const int32_t*
 /* kcore_decompose with explicit tuning (NULL = defaults) and optional statistics (NULL = none). */
 kcore_status kcore_decompose_ex(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
                                 const kcore_tuning* tuning, kcore_stats* stats, void* stream);
+
+/*
+ * kcore_decompose_batch -- coreness of many independent graphs in one launch
+ * sequence (all graphs advance round by round together; a converged graph
+ * simply has no frontier).  This form has no counterpart in the paper: it
+ * batches the same computation over many graphs.
+ *   num_graphs     G >= 0 (G == 0 is a no-op).
+ *   graph_vtx_off  DEVICE int64[G+1]: graph g owns global vertices
+ *                  [graph_vtx_off[g], graph_vtx_off[g+1]); graph_vtx_off[0] == 0;
+ *                  total N = graph_vtx_off[G] <= 2^31-1.
+ *   row_ptr        DEVICE int64[N+1]: GLOBAL offsets into col_idx.
+ *   col_idx        DEVICE int32: neighbour ids LOCAL to the graph (0 .. n_g-1).
+ *   out_core       DEVICE int32[N]: coreness, by global vertex id.
+ *   tuning         NULL: the tuning recorded for batches of this shape by
+ *                  kcore_autotune_batch / kcore_tuning_cache_set if any,
+ *                  else library defaults.
+ *   stats, stream  as for kcore_decompose_ex.
+ * Each graph's result equals the result of kcore_decompose on that graph alone.
+ * With KCORE_VALIDATE=1 the batch is checked first (ids inside their graph,
+ * symmetry, no loops or duplicates).
+ */
+kcore_status kcore_decompose_batch(int32_t num_graphs, const int64_t* graph_vtx_off, const int64_t* row_ptr,
+                                   const int32_t* col_idx, int32_t* out_core, const kcore_tuning* tuning,
+                                   kcore_stats* stats, void* stream);
+
+/*
+ * kcore_autotune_batch -- time launch-knob candidates (grid sizes, list
+ * capacity, tail threshold, class boundaries, poll chunk) on the caller's batch
+ * by coordinate descent, `reps` timed runs each (median), and record the best
+ * in the process-wide tuning cache under the batch's shape (G and the log2 of N
+ * and of the entry count).  Writes the best tuning and its time (ms).  Runs the
+ * decomposition many times; out_core holds a correct result on return.
+ */
+kcore_status kcore_autotune_batch(int32_t num_graphs, const int64_t* graph_vtx_off, const int64_t* row_ptr,
+                                  const int32_t* col_idx, int32_t* out_core, int32_t reps, kcore_tuning* best,
+                                  float* best_ms, void* stream);
+
+/* Set / get the cached tuning for batches of a shape (used to persist autotuner
+ * results across processes).  _get returns KCORE_E_AGAIN when there is no entry. */
+kcore_status kcore_tuning_cache_set(int32_t num_graphs, int64_t total_vertices, int64_t total_entries,
+                                    const kcore_tuning* tuning);
+kcore_status kcore_tuning_cache_get(int32_t num_graphs, int64_t total_vertices, int64_t total_entries,
+                                    kcore_tuning* tuning);
 
 /* Thread-local message for the last non-OK status returned on this thread. */
 const char* kcore_last_error(void);

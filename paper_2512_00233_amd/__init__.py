@@ -15,7 +15,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["decompose", "Tuning", "Stats", "KcoreError", "library_path", "load", "version"]
+__all__ = ["decompose", "decompose_batch", "autotune_batch", "tuning_cache_set", "tuning_cache_get", "Tuning",
+           "Stats", "KcoreError", "library_path", "load", "version"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libkcore.so")
@@ -47,7 +48,8 @@ class Tuning(ctypes.Structure):
         ("timing", ctypes.c_int32),
         ("list_cap", ctypes.c_int32),
         ("no_prune", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("no_graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -96,6 +98,15 @@ def load():
     lib.kcore_decompose32.argtypes = [i64, vp, vp, vp, vp]
     lib.kcore_decompose_ex.restype = i32
     lib.kcore_decompose_ex.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats), vp]
+    lib.kcore_decompose_batch.restype = i32
+    lib.kcore_decompose_batch.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats), vp]
+    lib.kcore_autotune_batch.restype = i32
+    lib.kcore_autotune_batch.argtypes = [i32, vp, vp, vp, vp, i32, ctypes.POINTER(Tuning),
+                                         ctypes.POINTER(ctypes.c_float), vp]
+    lib.kcore_tuning_cache_set.restype = i32
+    lib.kcore_tuning_cache_set.argtypes = [i32, i64, i64, ctypes.POINTER(Tuning)]
+    lib.kcore_tuning_cache_get.restype = i32
+    lib.kcore_tuning_cache_get.argtypes = [i32, i64, i64, ctypes.POINTER(Tuning)]
     lib.kcore_last_error.restype = ctypes.c_char_p
     lib.kcore_last_error.argtypes = []
     lib.kcore_version.restype = ctypes.c_char_p
@@ -160,3 +171,57 @@ def decompose(row_ptr, col_idx, out=None, tuning: Tuning | None = None, stats: S
                                       ctypes.byref(tuning) if tuning is not None else None,
                                       ctypes.byref(stats) if stats is not None else None, st))
     return out
+
+
+def _check_batch(graph_vtx_off, row_ptr, col_idx):
+    import torch
+    for t, name in ((graph_vtx_off, "graph_vtx_off"), (row_ptr, "row_ptr")):
+        if not t.is_cuda or t.dtype != torch.int64 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous int64 CUDA tensor")
+    if not col_idx.is_cuda or col_idx.dtype != torch.int32 or not col_idx.is_contiguous():
+        raise ValueError("col_idx must be a contiguous int32 CUDA tensor")
+    return graph_vtx_off.numel() - 1, row_ptr.numel() - 1
+
+
+def decompose_batch(graph_vtx_off, row_ptr, col_idx, out=None, tuning: Tuning | None = None,
+                    stats: Stats | None = None, stream=None):
+    """Coreness of many graphs at once (concatenated CSR, graph-local neighbour ids).
+
+    graph_vtx_off: int64 CUDA tensor [G+1]; row_ptr: int64 [N+1] (global offsets);
+    col_idx: int32 (local ids).  Returns out (int32 [N]).  With tuning None the
+    autotuner's cached choice for this batch shape is used when there is one.
+    """
+    import torch
+    lib = load()
+    G, N = _check_batch(graph_vtx_off, row_ptr, col_idx)
+    if out is None:
+        out = torch.empty(N, dtype=torch.int32, device=row_ptr.device)
+    col_ptr = col_idx.data_ptr() if col_idx.numel() else out.data_ptr()
+    _check(lib.kcore_decompose_batch(G, graph_vtx_off.data_ptr(), row_ptr.data_ptr(), col_ptr, out.data_ptr(),
+                                     ctypes.byref(tuning) if tuning is not None else None,
+                                     ctypes.byref(stats) if stats is not None else None, _stream_handle(stream)))
+    return out
+
+
+def autotune_batch(graph_vtx_off, row_ptr, col_idx, out=None, reps: int = 3, stream=None):
+    """Pick launch knobs for this batch shape by timing candidates; returns (Tuning, ms)."""
+    import torch
+    lib = load()
+    G, N = _check_batch(graph_vtx_off, row_ptr, col_idx)
+    if out is None:
+        out = torch.empty(N, dtype=torch.int32, device=row_ptr.device)
+    best, ms = Tuning(), ctypes.c_float()
+    _check(lib.kcore_autotune_batch(G, graph_vtx_off.data_ptr(), row_ptr.data_ptr(), col_idx.data_ptr(),
+                                    out.data_ptr(), reps, ctypes.byref(best), ctypes.byref(ms),
+                                    _stream_handle(stream)))
+    return best, float(ms.value)
+
+
+def tuning_cache_set(num_graphs: int, total_vertices: int, total_entries: int, tuning: Tuning):
+    _check(load().kcore_tuning_cache_set(num_graphs, total_vertices, total_entries, ctypes.byref(tuning)))
+
+
+def tuning_cache_get(num_graphs: int, total_vertices: int, total_entries: int):
+    t = Tuning()
+    st = load().kcore_tuning_cache_get(num_graphs, total_vertices, total_entries, ctypes.byref(t))
+    return t if st == 0 else None

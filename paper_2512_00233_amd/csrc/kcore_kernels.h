@@ -68,7 +68,8 @@ struct Ctl {
   int32_t seed_fill[kClasses];    // first-round (static) list sizes: vertices of degree >= 2 per class
   unsigned long long stats[16];
   int32_t error;                  // 1: the tail hit its round cap
-  int32_t pad[3];
+  int32_t rbase;                  // round number of slot 0 of the next chunk of round launches
+  int32_t pad[2];
 };
 enum Stat {
   ST_UPDATES = 0, ST_VISITS, ST_CHANGES, ST_ACTIVATIONS, ST_PRUNE_WRITES, ST_FULL_SCANS, ST_ROUNDS,

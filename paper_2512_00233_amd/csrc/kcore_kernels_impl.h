@@ -906,12 +906,33 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
 }
 
 // ------------------------------------------------------------------ kernels
+// Zero the control block (a kernel rather than a memset, so that the sequence
+// can be captured in a graph).
+__global__ void k_zero_ctl(Ctl* ctl) {
+  int32_t* p = reinterpret_cast<int32_t*>(ctl);
+  for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / sizeof(int32_t)); i += blockDim.x) p[i] = 0;
+}
+
+// Move the round base past a chunk of `k` round launches.
+__global__ void k_advance(Ctl* ctl, int32_t k) {
+  if (threadIdx.x == 0) ctl->rbase += k;
+}
+
+// Batched graphs: vbase[v] = first global vertex id of v's graph (one workgroup per graph).
+__global__ void k_vbase(const int64_t* graph_vtx_off, int32_t* vbase) {
+  const int64_t v0 = graph_vtx_off[blockIdx.x], v1 = graph_vtx_off[blockIdx.x + 1];
+  for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) vbase[v] = (int32_t)v0;
+}
+
 // est = degree, degree class, class populations (one atomic per workgroup and class).
 template <typename Off>
 __global__ __launch_bounds__(256) void k_init(Args<Off> a, int32_t r0, int32_t t0, int32_t t1, int32_t t2) {
   __shared__ uint32_t part[kClasses][256 / kWave];
   // the round after the first (all-vertices) round rebuilds its lists by compaction: no appends in the first round
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->overflow[(r0 + 1) % 3][0] = 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctl->overflow[(r0 + 1) % 3][0] = 1;
+    a.ctl->rbase = r0;
+  }
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   uint32_t p[kClasses] = {0, 0, 0, 0};
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
@@ -943,11 +964,12 @@ __global__ __launch_bounds__(256) void k_init(Args<Off> a, int32_t r0, int32_t t
 // owns a contiguous vertex range split among its wavefronts: a counting pass,
 // one atomic per workgroup and class, a writing pass without barriers.
 template <bool SEED, typename Off>
-__global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t round) {
+__global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
   constexpr int BLOCK = 256, NW = BLOCK / kWave;
   __shared__ int32_t wcnt[NW][kClasses];
   __shared__ int32_t bbase[kClasses];
   Ctl* ctl = a.ctl;
+  const int32_t round = ctl->rbase + slot;
   if (!SEED && ctl->overflow[round % 3][0] == 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int64_t chunk = ((a.n + gridDim.x - 1) / gridDim.x + kWave * NW - 1) / (kWave * NW) * (kWave * NW);
@@ -1002,10 +1024,11 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t round) {
 // One round, classes 0..2 (round number `round`).  A small frontier without
 // class-3 vertices is handed to the single-workgroup tail.
 template <int BLOCK, bool FIRST, bool BATCH, typename Off>
-__global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t round, int32_t collect_stats) {
+__global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t slot, int32_t collect_stats) {
   __shared__ unsigned long long red64[kLaneStats * (BLOCK / kWave)];
   __shared__ int32_t red[kKary * (BLOCK / kWave)];
   Ctl* ctl = a.ctl;
+  const int32_t round = ctl->rbase + slot;
   bool dense = false;
   const Frontier f = frontier_of<FIRST>(a, round, dense);
   if (blockIdx.x == 0 && threadIdx.x < 4) {
@@ -1037,12 +1060,13 @@ __global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t round, int
 // vertex.  Runs before k_round of the same round; a round handed to the tail
 // has no class-3 vertex, so this kernel then finds nothing to do.
 template <bool FIRST, bool BATCH, typename Off>
-__global__ __launch_bounds__(kBigBlock) void k_big(Args<Off> a, int32_t round, int32_t collect_stats) {
+__global__ __launch_bounds__(kBigBlock) void k_big(Args<Off> a, int32_t slot, int32_t collect_stats) {
   constexpr int BLOCK = kBigBlock;
   __shared__ int32_t hist[kHistBins];
   __shared__ int32_t red[kKary * (BLOCK / kWave)];
   __shared__ unsigned long long red64[kLaneStats * (BLOCK / kWave)];
   Ctl* ctl = a.ctl;
+  const int32_t round = ctl->rbase + slot;
   bool dense = false;
   const Frontier f = frontier_of<FIRST>(a, round, dense);
   if (f.n[3] == 0) return;
@@ -1090,6 +1114,55 @@ __global__ void k_validate(int64_t n, const Off* row_ptr, const int32_t* col, in
           break;
         }
         if (w < (int32_t)v) lo = mid + 1;
+        else hi = mid;
+      }
+      if (!found) {
+        atomicMin(err, 4);
+        break;
+      }
+    }
+  }
+}
+
+// Batched-graph precondition check: local ids inside their graph, no
+// self-loops, strictly increasing rows, symmetry (codes as k_validate).
+template <typename Off>
+__global__ void k_validate_batch(int64_t n, const Off* row_ptr, const int32_t* col, const int32_t* vbase,
+                                 int32_t* err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const Off b = row_ptr[v], e = row_ptr[v + 1];
+    if (e < b) {
+      atomicMin(err, 3);
+      continue;
+    }
+    const int32_t gb = vbase[v];
+    const int32_t vl = (int32_t)(v - gb);
+    for (Off j = b; j < e; ++j) {
+      const int32_t ul = col[j];
+      const int64_t u = (int64_t)gb + ul;
+      if (ul < 0 || u >= n || vbase[u] != gb) {
+        atomicMin(err, 1);
+        break;
+      }
+      if (u == v) {
+        atomicMin(err, 2);
+        break;
+      }
+      if (j > b && col[j - 1] >= ul) {
+        atomicMin(err, 3);
+        break;
+      }
+      Off lo = row_ptr[u], hi = row_ptr[u + 1];
+      bool found = false;
+      while (lo < hi) {
+        const Off mid = lo + (hi - lo) / 2;
+        const int32_t w = col[mid];
+        if (w == vl) {
+          found = true;
+          break;
+        }
+        if (w < vl) lo = mid + 1;
         else hi = mid;
       }
       if (!found) {

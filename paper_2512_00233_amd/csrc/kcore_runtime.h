@@ -20,6 +20,7 @@ struct Tuning {
   int timing;     // HIP events around every round launch
   int list_cap;   // sparse list capacity per class
   int prune;      // pruned adjacency on/off
+  int use_graph;  // capture chunks of round launches as hipGraphs
 };
 
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus);

@@ -55,7 +55,17 @@ struct Workspace {
   int64_t* host_nnz = nullptr;   // pinned
   int32_t epoch = 1;
   std::vector<hipEvent_t> events;  // timing mode: one pair per round launch
+  struct GraphEntry {
+    std::string key;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;  // captured chunks of round launches, by launch shape
   std::mutex mu;
+
+  void drop_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
 
   kcore_status need_events(size_t count) {
     while (events.size() < count) {
@@ -67,6 +77,7 @@ struct Workspace {
   }
 
   void release() {
+    drop_graphs();
     for (void* p : {(void*)stamp, (void*)cls, (void*)lists[0], (void*)lists[1], (void*)slist, (void*)plen,
                     (void*)plow, (void*)vbase, (void*)pruned})
       (void)hipFree(p);
@@ -148,6 +159,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.timing = 0;
   r.list_cap = 8192;
   r.prune = 1;
+  r.use_graph = 1;
   if (const char* e = std::getenv("KCORE_TAIL")) r.tail = std::atoi(e);
   if (t) {
     if (t->thread_max_deg > 0) r.t0 = std::min(t->thread_max_deg, kLaneMaxDeg);
@@ -162,6 +174,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
     r.timing = t->timing == 1;
     if (t->list_cap > 0) r.list_cap = t->list_cap;
     r.prune = t->no_prune != 1;
+    r.use_graph = t->no_graph != 1;
   }
   r.t0 = std::max(r.t0, 1);
   r.t1 = std::max(r.t1, r.t0);
@@ -179,6 +192,53 @@ static bool env_flag(const char* name) {
 // ------------------------------------------------------------------ driver
 constexpr int kBlock = 256;
 
+// Launch one chunk of K rounds (slots 0..K-1 relative to ctl->rbase) and
+// advance the round base.  With use_graph the chunk is captured once per
+// launch shape and replayed.
+template <bool BATCH, typename Off>
+static kcore_status launch_chunk(Workspace* ws, const Args<Off>& a, const Tuning& tu, int cgrid, int K,
+                                 int32_t collect, bool use_graph, hipStream_t st) {
+  auto enqueue = [&]() {
+    for (int i = 0; i < K; ++i) {
+      hipLaunchKernelGGL((k_compact<false, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, i);
+      hipLaunchKernelGGL((k_big<false, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, i, collect);
+      hipLaunchKernelGGL((k_round<kBlock, false, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, i, collect);
+    }
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a.ctl, K);
+  };
+  if (!use_graph) {
+    enqueue();
+    KC_HIP(hipGetLastError());
+    return KCORE_OK;
+  }
+  std::string key(reinterpret_cast<const char*>(&a), sizeof(a));
+  const int32_t shape[6] = {K, cgrid, tu.grid, tu.big_grid, collect, (int32_t)(BATCH * 2 + (sizeof(Off) == 8))};
+  key.append(reinterpret_cast<const char*>(shape), sizeof(shape));
+  for (auto& g : ws->graphs)
+    if (g.key == key) {
+      KC_HIP(hipGraphLaunch(g.exec, st));
+      return KCORE_OK;
+    }
+  hipGraph_t graph;
+  KC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  enqueue();
+  const hipError_t launch_err = hipGetLastError();
+  const hipError_t end_err = hipStreamEndCapture(st, &graph);
+  if (launch_err != hipSuccess) return hip_fail(launch_err, "round launch during capture");
+  if (end_err != hipSuccess) return hip_fail(end_err, "hipStreamEndCapture");
+  hipGraphExec_t exec;
+  const hipError_t inst_err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (inst_err != hipSuccess) return hip_fail(inst_err, "hipGraphInstantiate");
+  if (ws->graphs.size() >= 48) {
+    (void)hipGraphExecDestroy(ws->graphs.front().exec);
+    ws->graphs.erase(ws->graphs.begin());
+  }
+  ws->graphs.push_back({key, exec});
+  KC_HIP(hipGraphLaunch(exec, st));
+  return KCORE_OK;
+}
+
 // Every vertex of every graph (one graph: vbase unused) to its fixpoint.
 // row_ptr holds global edge offsets; with BATCH, col holds graph-local ids.
 template <bool BATCH, typename Off>
@@ -191,6 +251,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     ws->epoch = 1;
   }
   Args<Off> a;
+  std::memset(&a, 0, sizeof(a));
   a.n = n;
   a.row_ptr = row_ptr;
   a.col = col;
@@ -212,6 +273,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   const int32_t collect = stats ? 1 : 0;
   const bool trace = env_flag("KCORE_TRACE");
   const bool timing = tu.timing || trace;
+  const bool use_graph = tu.use_graph && !timing && st != nullptr;  // no capture on the null stream
   const int32_t r0 = ws->epoch;
   double first_ms = 0, later_ms = 0;
   unsigned long long first_st[4] = {0, 0, 0, 0};
@@ -219,12 +281,13 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     kcore_status s = ws->need_events(2 * 64);
     if (s != KCORE_OK) return s;
   }
-  KC_HIP(hipMemsetAsync(ws->ctl, 0, sizeof(Ctl), st));
+  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, st, ws->ctl);
   hipLaunchKernelGGL(k_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, r0, tu.t0, tu.t1, tu.t2);
-  hipLaunchKernelGGL((k_compact<true, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, r0);
+  hipLaunchKernelGGL((k_compact<true, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, 0);
   if (timing) KC_HIP(hipEventRecord(ws->events[0], st));
-  hipLaunchKernelGGL((k_big<true, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, r0, collect);
-  hipLaunchKernelGGL((k_round<kBlock, true, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, r0, collect);
+  hipLaunchKernelGGL((k_big<true, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, 0, collect);
+  hipLaunchKernelGGL((k_round<kBlock, true, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, 0, collect);
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, ws->ctl, 1);
   KC_HIP(hipGetLastError());
   unsigned long long prev_st[16];
   if (timing) {
@@ -245,23 +308,26 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     }
   }
   int64_t launches = 1;
-  int32_t r = r0 + 1;
   int K = trace ? 1 : tu.poll;
+  int32_t r = r0 + 1;
   for (;;) {
-    for (int i = 0; i < K; ++i) {
-      if (timing) KC_HIP(hipEventRecord(ws->events[2 * i], st));
-      hipLaunchKernelGGL((k_compact<false, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, r + i);
-      hipLaunchKernelGGL((k_big<false, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, r + i, collect);
-      hipLaunchKernelGGL((k_round<kBlock, false, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, r + i,
-                         collect);
-      if (timing) KC_HIP(hipEventRecord(ws->events[2 * i + 1], st));
+    if (timing) {
+      for (int i = 0; i < K; ++i) {
+        // one round per event pair: launch the slot, then move the base by one
+        KC_HIP(hipEventRecord(ws->events[2 * i], st));
+        kcore_status s = launch_chunk<BATCH, Off>(ws, a, tu, cgrid, 1, collect, false, st);
+        if (s != KCORE_OK) return s;
+        KC_HIP(hipEventRecord(ws->events[2 * i + 1], st));
+      }
+    } else {
+      kcore_status s = launch_chunk<BATCH, Off>(ws, a, tu, cgrid, K, collect, use_graph, st);
+      if (s != KCORE_OK) return s;
     }
-    KC_HIP(hipGetLastError());
     launches += K;
-    r += K;
     KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     KC_HIP(hipStreamSynchronize(st));
     const Ctl& h = *ws->host_ctl;
+    r = h.rbase;
     if (timing) {
       for (int i = 0; i < K; ++i) {
         float ms = 0;
@@ -353,6 +419,184 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
   return run_rounds<false, Off>(ws, n, nnz, row_ptr, col, out, tu, stats, st);
 }
 
+template <typename Off>
+static kcore_status validate_batch(Workspace* ws, int64_t n, const Off* row_ptr, const int32_t* col,
+                                   hipStream_t st) {
+  const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
+  KC_HIP(hipMemsetAsync(ws->verr, 0x7f, sizeof(int32_t), st));
+  hipLaunchKernelGGL(k_validate_batch<Off>, dim3(grid), dim3(kBlock), 0, st, n, row_ptr, col, ws->vbase, ws->verr);
+  KC_HIP(hipGetLastError());
+  KC_HIP(hipMemcpyAsync(ws->host_verr, ws->verr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  KC_HIP(hipStreamSynchronize(st));
+  const int32_t code = *ws->host_verr;
+  if (code != 0x7f7f7f7f) {
+    static const char* what[] = {"", "neighbour id outside its graph", "self-loop", "row not strictly increasing",
+                                 "graph not symmetric"};
+    return fail(KCORE_E_INVALID, std::string("KCORE_VALIDATE: ") + what[std::min(code, 4)]);
+  }
+  return KCORE_OK;
+}
+
+// ------------------------------------------------------------------ tuning cache (autotuner results)
+struct TuneEntry {
+  int32_t G;
+  int32_t logn, lognnz;  // log2 buckets of the vertex and entry counts
+  kcore_tuning t;
+};
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+
+static int ilog2(int64_t x) {
+  int l = 0;
+  while (x > 1) {
+    x >>= 1;
+    ++l;
+  }
+  return l;
+}
+
+static bool tune_lookup(int32_t G, int64_t n, int64_t nnz, kcore_tuning* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& e : g_tune)
+    if (e.G == G && e.logn == ilog2(n) && e.lognnz == ilog2(nnz)) {
+      *out = e.t;
+      return true;
+    }
+  return false;
+}
+
+static void tune_store(int32_t G, int64_t n, int64_t nnz, const kcore_tuning& t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& e : g_tune)
+    if (e.G == G && e.logn == ilog2(n) && e.lognnz == ilog2(nnz)) {
+      e.t = t;
+      return;
+    }
+  g_tune.push_back({G, ilog2(n), ilog2(nnz), t});
+}
+
+// Batched decomposition: read the sizes, build the per-vertex graph base, run.
+static kcore_status batch_prepare(Workspace* ws, int32_t G, const int64_t* gvo, const int64_t* row_ptr,
+                                  int64_t* n_out, int64_t* nnz_out, hipStream_t st) {
+  KC_HIP(hipMemcpyAsync(ws->host_nnz, gvo + G, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  KC_HIP(hipStreamSynchronize(st));
+  const int64_t n = *ws->host_nnz;
+  if (n < 0 || n > INT32_MAX) return fail(KCORE_E_INVALID, "total vertex count must be in [0, 2^31-1]");
+  int64_t nnz = 0;
+  if (n > 0) {
+    KC_HIP(hipMemcpyAsync(ws->host_nnz, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    KC_HIP(hipStreamSynchronize(st));
+    nnz = *ws->host_nnz;
+    if (nnz < 0) return fail(KCORE_E_INVALID, "row_ptr[N] is negative");
+  }
+  *n_out = n;
+  *nnz_out = nnz;
+  if (n == 0) return KCORE_OK;
+  kcore_status s = ensure_capacity(ws, n, nnz, true, st);
+  if (s != KCORE_OK) return s;
+  hipLaunchKernelGGL(k_vbase, dim3(G), dim3(256), 0, st, gvo, ws->vbase);
+  KC_HIP(hipGetLastError());
+  return KCORE_OK;
+}
+
+static kcore_status batch_impl(int32_t G, const int64_t* gvo, const int64_t* row_ptr, const int32_t* col,
+                               int32_t* out, const kcore_tuning* tuning, kcore_stats* stats, hipStream_t st) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (G < 0) return fail(KCORE_E_INVALID, "num_graphs must be >= 0");
+  if (G == 0) return KCORE_OK;
+  if (!gvo || !row_ptr || !col || !out) return fail(KCORE_E_INVALID, "null pointer argument");
+  Workspace* ws = nullptr;
+  kcore_status s = get_workspace(&ws);
+  if (s != KCORE_OK) return s;
+  std::lock_guard<std::mutex> lk(ws->mu);
+  int64_t n = 0, nnz = 0;
+  s = batch_prepare(ws, G, gvo, row_ptr, &n, &nnz, st);
+  if (s != KCORE_OK || n == 0) return s;
+  if (env_flag("KCORE_VALIDATE")) {
+    s = validate_batch<int64_t>(ws, n, row_ptr, col, st);
+    if (s != KCORE_OK) return s;
+  }
+  kcore_tuning cached;
+  const kcore_tuning* use = tuning;
+  if (!use && tune_lookup(G, n, nnz, &cached)) use = &cached;
+  const Tuning tu = resolve_tuning(use, ws->num_cus);
+  return run_rounds<true, int64_t>(ws, n, nnz, row_ptr, col, out, tu, stats, st);
+}
+
+// Coordinate descent over the launch knobs; each candidate is timed (median
+// of `reps` runs, HIP events on the stream) on the caller's batch.
+static kcore_status autotune_impl(int32_t G, const int64_t* gvo, const int64_t* row_ptr, const int32_t* col,
+                                  int32_t* out, int32_t reps, kcore_tuning* best, float* best_ms, hipStream_t st) {
+  if (G <= 0 || !gvo || !row_ptr || !col || !out || !best) return fail(KCORE_E_INVALID, "bad autotune arguments");
+  reps = std::max(1, std::min(reps, 15));
+  Workspace* ws = nullptr;
+  kcore_status s = get_workspace(&ws);
+  if (s != KCORE_OK) return s;
+  int cus = ws->num_cus;
+  hipEvent_t e0, e1;
+  KC_HIP(hipEventCreate(&e0));
+  KC_HIP(hipEventCreate(&e1));
+  auto measure = [&](const kcore_tuning& t, float* ms) -> kcore_status {
+    std::vector<float> v;
+    for (int i = 0; i < reps + 1; ++i) {
+      KC_HIP(hipEventRecord(e0, st));
+      kcore_status r = batch_impl(G, gvo, row_ptr, col, out, &t, nullptr, st);
+      if (r != KCORE_OK) return r;
+      KC_HIP(hipEventRecord(e1, st));
+      KC_HIP(hipEventSynchronize(e1));
+      float x = 0;
+      KC_HIP(hipEventElapsedTime(&x, e0, e1));
+      if (i > 0) v.push_back(x);  // first run warms the workspace and the graph cache
+    }
+    std::sort(v.begin(), v.end());
+    *ms = v[v.size() / 2];
+    return KCORE_OK;
+  };
+  kcore_tuning cur;
+  std::memset(&cur, 0, sizeof(cur));
+  float cur_ms = 0;
+  s = measure(cur, &cur_ms);
+  if (s != KCORE_OK) return s;
+  struct Knob {
+    int32_t kcore_tuning::*field;
+    std::vector<int32_t> values;
+  };
+  const std::vector<Knob> knobs = {
+      {&kcore_tuning::grid_blocks, {4 * cus, 8 * cus, 16 * cus}},
+      {&kcore_tuning::big_grid_blocks, {2 * cus, 4 * cus, 8 * cus}},
+      {&kcore_tuning::list_cap, {2048, 8192, 32768}},
+      {&kcore_tuning::tail_threshold, {512, 2048, 8192}},
+      {&kcore_tuning::group_max_deg, {32, 64}},
+      {&kcore_tuning::wave_max_deg, {256, 512}},
+      {&kcore_tuning::rounds_per_poll, {2, 4, 8}},
+  };
+  for (const auto& k : knobs) {
+    for (int32_t val : k.values) {
+      kcore_tuning cand = cur;
+      cand.*(k.field) = val;
+      float ms = 0;
+      s = measure(cand, &ms);
+      if (s != KCORE_OK) return s;
+      if (ms < cur_ms * 0.99f) {
+        cur = cand;
+        cur_ms = ms;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *best = cur;
+  if (best_ms) *best_ms = cur_ms;
+  int64_t n = 0, nnz = 0;
+  {
+    std::lock_guard<std::mutex> lk(ws->mu);
+    s = batch_prepare(ws, G, gvo, row_ptr, &n, &nnz, st);
+    if (s != KCORE_OK) return s;
+  }
+  tune_store(G, n, nnz, cur);
+  return KCORE_OK;
+}
+
 }  // namespace kcore
 
 using namespace kcore;
@@ -372,6 +616,33 @@ kcore_status kcore_decompose32(int64_t n, const int32_t* row_ptr, const int32_t*
 kcore_status kcore_decompose_ex(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
                                 const kcore_tuning* tuning, kcore_stats* stats, void* stream) {
   return decompose_impl<int64_t>(n, row_ptr, col_idx, out_core, tuning, stats, (hipStream_t)stream);
+}
+
+kcore_status kcore_decompose_batch(int32_t num_graphs, const int64_t* graph_vtx_off, const int64_t* row_ptr,
+                                   const int32_t* col_idx, int32_t* out_core, const kcore_tuning* tuning,
+                                   kcore_stats* stats, void* stream) {
+  return batch_impl(num_graphs, graph_vtx_off, row_ptr, col_idx, out_core, tuning, stats, (hipStream_t)stream);
+}
+
+kcore_status kcore_autotune_batch(int32_t num_graphs, const int64_t* graph_vtx_off, const int64_t* row_ptr,
+                                  const int32_t* col_idx, int32_t* out_core, int32_t reps, kcore_tuning* best,
+                                  float* best_ms, void* stream) {
+  return autotune_impl(num_graphs, graph_vtx_off, row_ptr, col_idx, out_core, reps, best, best_ms,
+                       (hipStream_t)stream);
+}
+
+kcore_status kcore_tuning_cache_set(int32_t num_graphs, int64_t total_vertices, int64_t total_entries,
+                                    const kcore_tuning* tuning) {
+  if (!tuning || num_graphs <= 0) return fail(KCORE_E_INVALID, "bad tuning cache key or value");
+  tune_store(num_graphs, total_vertices, total_entries, *tuning);
+  return KCORE_OK;
+}
+
+kcore_status kcore_tuning_cache_get(int32_t num_graphs, int64_t total_vertices, int64_t total_entries,
+                                    kcore_tuning* tuning) {
+  if (!tuning) return fail(KCORE_E_INVALID, "null tuning");
+  if (!tune_lookup(num_graphs, total_vertices, total_entries, tuning)) return fail(KCORE_E_AGAIN, "no entry");
+  return KCORE_OK;
 }
 
 const char* kcore_last_error(void) { return g_last_error.c_str(); }

@@ -20,7 +20,7 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ["kcore_decompose", "kcore_decompose32", "kcore_last_error"]:
+    for required in ["kcore_decompose", "kcore_decompose32", "kcore_decompose_batch", "kcore_last_error"]:
         assert required in names
 
 
