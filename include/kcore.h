@@ -161,6 +161,104 @@ kcore_status kcore_tuning_cache_set(int32_t num_graphs, int64_t total_vertices, 
 kcore_status kcore_tuning_cache_get(int32_t num_graphs, int64_t total_vertices, int64_t total_entries,
                                     kcore_tuning* tuning);
 
+/* ------------------------------------------------------------------ serving
+ * A server decomposes a stream of independent graphs submitted from host
+ * memory.  This form has no counterpart in the paper: it runs the same
+ * computation as kcore_decompose_batch over graphs that arrive at different
+ * times.  It holds a vertex arena and an adjacency-entry arena in device
+ * memory, sized from a byte budget.  A request is admitted when both arenas
+ * have room for it (its device footprint is KCORE_SERVE_VERTEX_BYTES * (n+1) +
+ * KCORE_SERVE_ENTRY_BYTES * nnz bytes); its CSR is then copied in on a copy
+ * stream while the resident graphs keep computing, and at the next step
+ * boundary it joins the running rounds (continuous batching: graphs enter and
+ * leave between steps of a few rounds, the others are not restarted).  A graph
+ * whose frontier is empty leaves its slot: its result is copied to the
+ * caller's out_core on another copy stream and its arena space is reused.
+ * Each result equals kcore_decompose on that graph alone.
+ *
+ * Threads: one server thread per server drives the device; submit, poll, wait
+ * and stats may be called from any host thread.  No call on a server may be in
+ * progress or made once kcore_serve_destroy has been called on it.
+ */
+#define KCORE_SERVE_VERTEX_BYTES 41
+#define KCORE_SERVE_ENTRY_BYTES 8
+
+typedef struct kcore_serve_config {
+  int64_t hbm_budget_bytes;   /* device bytes for the arenas (0: min(64 GiB, half of the free memory)) */
+  int32_t max_slots;          /* graphs resident at once (0: 1024) */
+  int32_t max_queue;          /* submitted, not yet admitted requests before submit returns KCORE_E_AGAIN
+                                 (0: 65536) */
+  int32_t rounds_per_step;    /* rounds between two step boundaries (0: 8) */
+  int32_t entries_per_vertex; /* split of the budget: entry-arena slots per vertex-arena slot (0: 16) */
+  int32_t device;             /* HIP device ordinal */
+  int32_t reserved[5];
+  kcore_tuning tuning;        /* round-kernel knobs, as for kcore_decompose_ex (timing is ignored) */
+} kcore_serve_config;
+
+typedef struct kcore_server kcore_server;
+
+typedef struct kcore_completion {
+  uint64_t req_id;
+  int32_t status;     /* KCORE_OK, KCORE_E_CANCELLED, or KCORE_E_HIP after a device failure */
+  int32_t rounds;     /* rounds the graph spent resident (from joining to its last round) */
+  double latency_us;  /* submit -> result in out_core */
+  double queue_us;    /* submit -> admission into the arenas */
+} kcore_completion;
+
+typedef struct kcore_serve_report {
+  int64_t submitted;    /* accepted by kcore_serve_submit */
+  int64_t completed;    /* results delivered (status OK) */
+  int64_t cancelled;
+  int64_t rejected;     /* submit calls that returned an error */
+  int64_t queued;       /* waiting for admission now */
+  int64_t resident;     /* admitted and not yet completed now */
+  int64_t steps;        /* step launches */
+  int64_t rounds;       /* rounds run */
+  int64_t bytes_budget; /* arena bytes held on the device */
+  int64_t bytes_peak;   /* peak footprint of admitted requests */
+  double p50_us, p99_us, max_us, mean_us;  /* latency over completed requests */
+  double graphs_per_s;  /* completed / (last completion - first submit) */
+  int64_t reserved[4];
+} kcore_serve_report;
+
+/* Create a server (cfg may be NULL: defaults).  Allocates the arenas, three
+ * HIP streams of default priority and the server thread.  KCORE_E_NOMEM when
+ * the budget cannot be allocated. */
+kcore_status kcore_serve_create(const kcore_serve_config* cfg, kcore_server** out);
+
+/*
+ * Submit one graph.  row_ptr (int64[n+1], row_ptr[0] == 0), col_idx
+ * (int32[row_ptr[n]], ids in [0, n)) and out_core (int32[n]) are HOST
+ * pointers owned by the caller, kept alive and unmodified until the request's
+ * completion has been delivered by kcore_serve_poll or kcore_serve_wait.  Page-locked
+ * (pinned) memory lets the copies overlap with compute; pageable memory works
+ * but the copies then block the server thread.  The row offsets are read
+ * during the call (degree classes).  *out_req_id receives the request id.
+ * Errors: KCORE_E_INVALID (bad arguments; with KCORE_VALIDATE=1 also a CSR
+ * that breaks the preconditions), KCORE_E_TOO_LARGE (the graph cannot fit in
+ * the arenas even when they are empty), KCORE_E_AGAIN (queue full),
+ * KCORE_E_HIP (the server failed earlier).  n == 0 completes at once.
+ */
+kcore_status kcore_serve_submit(kcore_server* server, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                                int32_t* out_core, uint64_t* out_req_id);
+
+/* Non-blocking: move up to `max` completions (in completion order) into out;
+ * *n_out receives how many.  Each completion is delivered once, by poll or by wait. */
+kcore_status kcore_serve_poll(kcore_server* server, kcore_completion* out, int32_t max, int32_t* n_out);
+
+/* Block until request req_id completes (timeout_us < 0: no limit) and deliver
+ * its completion.  KCORE_E_TIMEOUT if it did not complete in time (it stays
+ * pending), KCORE_E_INVALID for an unknown or already delivered id. */
+kcore_status kcore_serve_wait(kcore_server* server, uint64_t req_id, int64_t timeout_us, kcore_completion* out);
+
+/* Counters and latency percentiles so far. */
+kcore_status kcore_serve_stats(kcore_server* server, kcore_serve_report* out);
+
+/* Stop the server: queued and in-flight requests are cancelled (their
+ * out_core contents are unspecified), the device work is drained, every
+ * resource is freed. */
+kcore_status kcore_serve_destroy(kcore_server* server);
+
 /* Thread-local message for the last non-OK status returned on this thread. */
 const char* kcore_last_error(void);
 

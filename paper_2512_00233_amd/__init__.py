@@ -16,7 +16,7 @@ import ctypes
 import os
 
 __all__ = ["decompose", "decompose_batch", "autotune_batch", "tuning_cache_set", "tuning_cache_get", "Tuning",
-           "Stats", "KcoreError", "library_path", "load", "version"]
+           "Stats", "KcoreError", "Server", "ServeConfig", "Completion", "library_path", "load", "version"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libkcore.so")
@@ -79,6 +79,56 @@ class Stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}
 
 
+class ServeConfig(ctypes.Structure):
+    """Mirror of ``kcore_serve_config`` (zero = library default)."""
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_int64),
+        ("max_slots", ctypes.c_int32),
+        ("max_queue", ctypes.c_int32),
+        ("rounds_per_step", ctypes.c_int32),
+        ("entries_per_vertex", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
+        ("tuning", Tuning),
+    ]
+
+
+class Completion(ctypes.Structure):
+    """Mirror of ``kcore_completion``."""
+    _fields_ = [
+        ("req_id", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("rounds", ctypes.c_int32),
+        ("latency_us", ctypes.c_double),
+        ("queue_us", ctypes.c_double),
+    ]
+
+
+class ServeReport(ctypes.Structure):
+    """Mirror of ``kcore_serve_report``."""
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("cancelled", ctypes.c_int64),
+        ("rejected", ctypes.c_int64),
+        ("queued", ctypes.c_int64),
+        ("resident", ctypes.c_int64),
+        ("steps", ctypes.c_int64),
+        ("rounds", ctypes.c_int64),
+        ("bytes_budget", ctypes.c_int64),
+        ("bytes_peak", ctypes.c_int64),
+        ("p50_us", ctypes.c_double),
+        ("p99_us", ctypes.c_double),
+        ("max_us", ctypes.c_double),
+        ("mean_us", ctypes.c_double),
+        ("graphs_per_s", ctypes.c_double),
+        ("reserved", ctypes.c_int64 * 4),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
 def library_path() -> str:
     return _LIB_PATH
 
@@ -113,6 +163,18 @@ def load():
     lib.kcore_version.argtypes = []
     lib.kcore_release_workspace.restype = i32
     lib.kcore_release_workspace.argtypes = []
+    lib.kcore_serve_create.restype = i32
+    lib.kcore_serve_create.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(vp)]
+    lib.kcore_serve_submit.restype = i32
+    lib.kcore_serve_submit.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)]
+    lib.kcore_serve_poll.restype = i32
+    lib.kcore_serve_poll.argtypes = [vp, ctypes.POINTER(Completion), i32, ctypes.POINTER(i32)]
+    lib.kcore_serve_wait.restype = i32
+    lib.kcore_serve_wait.argtypes = [vp, ctypes.c_uint64, i64, ctypes.POINTER(Completion)]
+    lib.kcore_serve_stats.restype = i32
+    lib.kcore_serve_stats.argtypes = [vp, ctypes.POINTER(ServeReport)]
+    lib.kcore_serve_destroy.restype = i32
+    lib.kcore_serve_destroy.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -225,3 +287,93 @@ def tuning_cache_get(num_graphs: int, total_vertices: int, total_entries: int):
     t = Tuning()
     st = load().kcore_tuning_cache_get(num_graphs, total_vertices, total_entries, ctypes.byref(t))
     return t if st == 0 else None
+
+
+def _host_ptr(x, dtype_name: str, name: str):
+    """Address of a contiguous host array (numpy array or CPU torch tensor) of the given dtype."""
+    if hasattr(x, "data_ptr") and hasattr(x, "is_cuda"):
+        if x.is_cuda or str(x.dtype) != f"torch.{dtype_name}" or not x.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous host {dtype_name} tensor")
+        return x.data_ptr(), x.numel()
+    import numpy as np
+    if not isinstance(x, np.ndarray) or x.dtype != np.dtype(dtype_name) or not x.flags.c_contiguous:
+        raise ValueError(f"{name} must be a C-contiguous numpy {dtype_name} array")
+    return x.ctypes.data, x.size
+
+
+class Server:
+    """Continuous-batching decomposition server (``kcore_serve_*``).
+
+    Graphs are submitted from host memory (numpy arrays or CPU torch tensors,
+    pinned ones let copies overlap); results land in the caller's ``out``
+    array.  The arrays are kept referenced here until the request's completion
+    has been delivered by :meth:`poll` or :meth:`wait`.
+    """
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_slots: int = 0, max_queue: int = 0, rounds_per_step: int = 0,
+                 entries_per_vertex: int = 0, device: int = 0, tuning: Tuning | None = None):
+        lib = load()
+        cfg = ServeConfig(hbm_budget_bytes=hbm_budget_bytes, max_slots=max_slots, max_queue=max_queue,
+                          rounds_per_step=rounds_per_step, entries_per_vertex=entries_per_vertex, device=device)
+        if tuning is not None:
+            cfg.tuning = tuning
+        h = ctypes.c_void_p()
+        _check(lib.kcore_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, row_ptr, col_idx, out) -> int:
+        """Queue one graph (int64 row_ptr[n+1], int32 col_idx, int32 out[n]); returns the request id."""
+        if self._h is None:
+            raise RuntimeError("server closed")
+        rp, nrp = _host_ptr(row_ptr, "int64", "row_ptr")
+        ci, _ = _host_ptr(col_idx, "int32", "col_idx")
+        op, nout = _host_ptr(out, "int32", "out")
+        n = nrp - 1
+        if n < 0 or nout != n:
+            raise ValueError("row_ptr must have n+1 entries and out n entries")
+        rid = ctypes.c_uint64()
+        _check(load().kcore_serve_submit(self._h, n, rp, ci, op, ctypes.byref(rid)))
+        self._keep[rid.value] = (row_ptr, col_idx, out)
+        return rid.value
+
+    def poll(self, max_items: int = 256) -> list:
+        """Completions delivered since the last call (non-blocking)."""
+        buf = (Completion * max_items)()
+        got = ctypes.c_int32()
+        _check(load().kcore_serve_poll(self._h, buf, max_items, ctypes.byref(got)))
+        res = [buf[i] for i in range(got.value)]
+        for c in res:
+            self._keep.pop(c.req_id, None)
+        return res
+
+    def wait(self, req_id: int, timeout_s: float | None = None) -> Completion:
+        """Block until req_id completes; raises KcoreError (KCORE_E_TIMEOUT) when the time runs out."""
+        c = Completion()
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        _check(load().kcore_serve_wait(self._h, req_id, us, ctypes.byref(c)))
+        self._keep.pop(c.req_id, None)
+        return c
+
+    def stats(self) -> dict:
+        r = ServeReport()
+        _check(load().kcore_serve_stats(self._h, ctypes.byref(r)))
+        return r.as_dict()
+
+    def close(self):
+        if self._h is not None:
+            _check(load().kcore_serve_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -38,6 +38,12 @@
 //    (the GPU analogue of FastK's switch to sequential processing, Sec. IV).
 //  * Batched graphs: neighbour ids are graph-local; a per-vertex base offset
 //    turns them into global ids (pruned lists store global ids).
+//  * Served graphs: graphs join a running sequence of rounds between two
+//    launches.  Their vertices are stamped with the next round number, and that
+//    round rebuilds its lists by compaction, so a new graph's first round is a
+//    compaction round over all of its vertices.  Every activation also records
+//    the round in a per-graph word, so the host can tell which graphs have no
+//    work left and retire them while the others keep running.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -69,7 +75,8 @@ struct Ctl {
   unsigned long long stats[16];
   int32_t error;                  // 1: the tail hit its round cap
   int32_t rbase;                  // round number of slot 0 of the next chunk of round launches
-  int32_t pad[2];
+  int32_t tail_pending;           // rounds run by a tail since the last base advance (stamps up to rbase + this)
+  int32_t nhi;                    // served graphs: vertex-id bound of the live slots (compaction range)
 };
 enum Stat {
   ST_UPDATES = 0, ST_VISITS, ST_CHANGES, ST_ACTIVATIONS, ST_PRUNE_WRITES, ST_FULL_SCANS, ST_ROUNDS,
@@ -100,6 +107,14 @@ struct Args {
   int32_t list_cap;    // sparse list capacity per class before overflow
   int32_t one_sided;
   int32_t prune;       // 0 disables the pruned adjacency
+  int32_t* gact;       // served graphs: per graph (indexed by its base vertex) the last round it has work for
+};
+
+// A served graph's place in the arenas.
+struct SlotDesc {
+  int64_t eb;  // first entry of its adjacency in the entry arena
+  int32_t vb;  // first vertex id in the vertex arena (its rows are vb .. vb+n-1; row_ptr[vb+n] ends the last row)
+  int32_t n;   // vertices
 };
 
 }  // namespace kcore

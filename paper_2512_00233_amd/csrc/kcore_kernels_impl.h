@@ -82,7 +82,7 @@ __device__ __forceinline__ Sink make_sink(const Args<Off>& a, int32_t next_round
 // active lane of the wavefront must call this.
 template <int N, typename Off>
 __device__ __forceinline__ void activate_batch(const Args<Off>& a, const Sink& s, const int32_t (&v)[N],
-                                               const bool (&want)[N], LaneStats& st) {
+                                               const bool (&want)[N], LaneStats& st, int32_t gb) {
   bool anyw = false;
 #pragma unroll
   for (int i = 0; i < N; ++i) anyw |= want[i];
@@ -96,6 +96,8 @@ __device__ __forceinline__ void activate_batch(const Args<Off>& a, const Sink& s
 #pragma unroll
   for (int i = 0; i < N; ++i) first |= (p[i] < s.stamp ? 1u : 0u) << i;
   st.v[ST_ACTIVATIONS] += __popc(first);
+  // served graphs: the graph has work in the next round (all candidates share the activating vertex's graph)
+  if (a.gact && first) a.gact[gb] = s.stamp;
   const bool compact_next = s.overflow && *(volatile int32_t*)s.overflow;
   if (compact_next || !ballot(first != 0)) return;
 #pragma unroll
@@ -258,7 +260,7 @@ __device__ __forceinline__ void upd_lane(const Args<Off>& a, const Sink& s, int3
   bool w[kLaneMaxDeg];
 #pragma unroll
   for (int i = 0; i < kLaneMaxDeg; ++i) w[i] = changed && i < d && decide(a, c[i], x[i], e, h, dense, round);
-  activate_batch<kLaneMaxDeg>(a, s, c, w, st);
+  activate_batch<kLaneMaxDeg>(a, s, c, w, st, gb);
 }
 
 // ------------------------------------------------------------------ class 1: 16-lane group per vertex
@@ -298,7 +300,7 @@ __device__ __forceinline__ void upd_group(const Args<Off>& a, const Sink& s, int
   bool w[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) w[r] = changed && (gl + G * r < d) && decide(a, c[r], x[r], e, h, dense, round);
-  activate_batch<R>(a, s, c, w, st);
+  activate_batch<R>(a, s, c, w, st, gb);
 }
 
 // ------------------------------------------------------------------ class 2: wavefront per vertex
@@ -372,7 +374,7 @@ __device__ __forceinline__ void upd_wave(const Args<Off>& a, const Sink& s, int3
   bool w[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) w[i] = (lane + kWave * i < len) && decide(a, c[i], x[i], e, h, dense, round);
-  activate_batch<R>(a, s, c, w, st);
+  activate_batch<R>(a, s, c, w, st, gb);
 }
 
 // ------------------------------------------------------------------ class 3: workgroup per vertex
@@ -707,7 +709,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
     bool w[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) w[i] = (tid + BLOCK * i < len) && decide(a, c[i], x[i], e, h, dense, round);
-    activate_batch<R>(a, s, c, w, st);
+    activate_batch<R>(a, s, c, w, st, gb);
     return;
   }
   // streaming pass over the list: activation and/or rebuilding the pruned list
@@ -730,7 +732,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
     }
     if (changed) {
       bool w[1] = {(j < len) && decide(a, v[0], xv, e, h, dense, round)};
-      activate_batch<1>(a, s, v, w, st);
+      activate_batch<1>(a, s, v, w, st, gb);
     }
   }
   if (rebuild_pass && tid == 0) {
@@ -791,7 +793,7 @@ __device__ __forceinline__ void upd_big_lite(const Args<Off>& a, const Sink& s, 
       v[0] = off + src[j];
       w[0] = decide(a, v[0], a.est[v[0]], e, h, false, round);
     }
-    activate_batch<1>(a, s, v, w, st);
+    activate_batch<1>(a, s, v, w, st, gb);
   }
 }
 
@@ -893,13 +895,14 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
     if (t > 0 && tid < kClasses) ctl->tail_cnt[t & 1][tid] = 0;  // reused by round t+2
     __syncthreads();
   }
-  if (tid < 4) {
-    ctl->cnt[(round + 1) % 3][tid] = 0;
-    ctl->cnt[(round + 2) % 3][tid] = 0;
-    ctl->overflow[(round + 1) % 3][tid] = 0;
-    ctl->overflow[(round + 2) % 3][tid] = 0;
+  // Nothing is left anywhere: clear every round slot (the round base then skips
+  // past the stamps the tail used, so none of them is read again).
+  if (tid < 12) {
+    ctl->cnt[tid / 4][tid % 4] = 0;
+    ctl->overflow[tid / 4][tid % 4] = 0;
   }
   if (tid == 0) {
+    ctl->tail_pending += t;
     atomicAdd(&ctl->stats[ST_TAIL_ROUNDS], (unsigned long long)t);
     atomicAdd(&ctl->stats[ST_ROUNDS], (unsigned long long)t);
   }
@@ -913,9 +916,13 @@ __global__ void k_zero_ctl(Ctl* ctl) {
   for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / sizeof(int32_t)); i += blockDim.x) p[i] = 0;
 }
 
-// Move the round base past a chunk of `k` round launches.
+// Move the round base past a chunk of `k` round launches and past the rounds
+// a tail ran inside it.
 __global__ void k_advance(Ctl* ctl, int32_t k) {
-  if (threadIdx.x == 0) ctl->rbase += k;
+  if (threadIdx.x == 0) {
+    ctl->rbase += k + ctl->tail_pending;
+    ctl->tail_pending = 0;
+  }
 }
 
 // Batched graphs: vbase[v] = first global vertex id of v's graph (one workgroup per graph).
@@ -972,9 +979,10 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
   const int32_t round = ctl->rbase + slot;
   if (!SEED && ctl->overflow[round % 3][0] == 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
-  const int64_t chunk = ((a.n + gridDim.x - 1) / gridDim.x + kWave * NW - 1) / (kWave * NW) * (kWave * NW);
+  const int64_t n = a.gact ? (int64_t)ctl->nhi : a.n;  // served graphs: the range of the live slots
+  const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + kWave * NW - 1) / (kWave * NW) * (kWave * NW);
   const int64_t wchunk = chunk / NW;
-  const int64_t w0 = (int64_t)blockIdx.x * chunk + wave * wchunk, w1 = min(a.n, w0 + wchunk);
+  const int64_t w0 = (int64_t)blockIdx.x * chunk + wave * wchunk, w1 = min(n, w0 + wchunk);
   auto cls_if_active = [&](int64_t v) -> int {
     if (v >= w1) return kClasses;
     const bool act = SEED ? a.est[v] >= 2 : a.stamp[v] == round;
@@ -1171,6 +1179,71 @@ __global__ void k_validate_batch(int64_t n, const Off* row_ptr, const int32_t* c
       }
     }
   }
+}
+
+// ------------------------------------------------------------------ served graphs
+// Graphs join the running rounds between two launches, each into a slot of the
+// vertex arena (vb .. vb+n, the last entry holding the row end) and of the
+// entry arena (eb ..).  The slot's graph-local row offsets have just been
+// copied to row_ptr[vb .. vb+n].
+
+// New slots (blockIdx.y = slot): est = degree, class, no pruned list, graph
+// base, and for every vertex of degree >= 2 a stamp of the next round, which
+// is then the graph's first round; the graph's activity word gets it too.
+template <typename Off>
+__global__ __launch_bounds__(256) void k_slot_init(Args<Off> a, const SlotDesc* slots, int32_t t0, int32_t t1,
+                                                   int32_t t2) {
+  const SlotDesc sd = slots[blockIdx.y];
+  const int32_t r = a.ctl->rbase;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < sd.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = sd.vb + i;
+    const int32_t d = (int32_t)(a.row_ptr[v + 1] - a.row_ptr[v]);
+    a.est[v] = d;
+    a.plen[v] = 0;
+    a.cls[v] = d <= t0 ? 0 : (d <= t1 ? 1 : (d <= t2 ? 2 : 3));
+    const_cast<int32_t*>(a.vbase)[v] = sd.vb;
+    if (d >= 2) a.stamp[v] = r;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.gact[sd.vb] = r;
+}
+
+// Graph-local row offsets of the new slots -> entry-arena offsets (after k_slot_init has read them).
+__global__ __launch_bounds__(256) void k_slot_shift(int64_t* row_ptr, const SlotDesc* slots) {
+  const SlotDesc sd = slots[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= sd.n; i += (int64_t)gridDim.x * blockDim.x)
+    row_ptr[sd.vb + i] += sd.eb;
+}
+
+// After slots joined (or left): new class populations, so the next round
+// rebuilds its lists by compaction over the live vertex range; its append
+// counters start from zero.
+__global__ void k_serve_join(Ctl* ctl, int32_t p0, int32_t p1, int32_t p2, int32_t p3, int32_t nhi) {
+  const int k = threadIdx.x;
+  const int32_t r = ctl->rbase;
+  if (k < kClasses) {
+    ctl->pop[k] = k == 0 ? p0 : (k == 1 ? p1 : (k == 2 ? p2 : p3));
+    ctl->ccnt[r & 1][k] = 0;
+    ctl->cnt[(r + 1) % 3][k] = 0;
+    ctl->overflow[(r + 1) % 3][k] = 0;
+  }
+  if (k == 0) {
+    ctl->overflow[r % 3][0] = 1;
+    ctl->nhi = nhi;
+  }
+}
+
+// Activity word of every slot's graph (the host compares it with the round base).
+__global__ void k_slot_status(const int32_t* gact, const int32_t* slot_vb, int32_t nslots, int32_t* out) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nslots; i += gridDim.x * blockDim.x)
+    out[i] = slot_vb[i] >= 0 ? gact[slot_vb[i]] : 0;
+}
+
+// Control block of a server: zero, round base r0.
+__global__ void k_serve_reset(Ctl* ctl, int32_t r0) {
+  int32_t* p = reinterpret_cast<int32_t*>(ctl);
+  for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / sizeof(int32_t)); i += blockDim.x) p[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) ctl->rbase = r0;
 }
 
 }  // namespace kcore

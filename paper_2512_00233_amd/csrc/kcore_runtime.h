@@ -1,7 +1,12 @@
 // Internal host-side declarations shared by the runtime translation units.
 #pragma once
 
+#include <stddef.h>
+#include <stdint.h>
+
 #include <string>
+
+#include <hip/hip_runtime_api.h>
 
 #include "../../include/kcore.h"
 
@@ -25,5 +30,58 @@ struct Tuning {
 
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus);
 kcore_status fail(kcore_status s, const std::string& msg);
+kcore_status hip_fail(hipError_t e, const char* what);
+
+// ------------------------------------------------------------------ served graphs
+// Device side of a server: a vertex arena and an entry arena holding every
+// resident graph, the round kernels' state over them, and the captured step.
+struct ServeArena {
+  int device = 0;
+  int num_cus = 0;
+  int64_t nv = 0;       // vertex arena capacity (ids), < 2^31
+  int64_t ne = 0;       // entry arena capacity
+  int32_t max_slots = 0;
+  Tuning tu{};
+  size_t bytes = 0;     // device bytes held
+  // vertex arena
+  int64_t* row_ptr = nullptr;
+  int32_t* est = nullptr;
+  int32_t* stamp = nullptr;
+  uint8_t* cls = nullptr;
+  int32_t* lists[2] = {nullptr, nullptr};
+  int32_t* plen = nullptr;
+  int32_t* plow = nullptr;
+  int32_t* vbase = nullptr;
+  int32_t* gact = nullptr;
+  // entry arena
+  int32_t* col = nullptr;
+  int32_t* pruned = nullptr;
+  // control and slot tables
+  void* ctl = nullptr;          // Ctl
+  void* slots = nullptr;        // SlotDesc[max_slots] of the slots joining at a boundary
+  int32_t* slot_vb = nullptr;   // [max_slots] base vertex per slot index (-1: none)
+  int32_t* status = nullptr;    // [max_slots] activity words
+  void* step_exec = nullptr;    // hipGraphExec_t of one step
+  int32_t step_rounds = 0;
+};
+
+// Bytes of device memory per vertex and per adjacency entry of a resident graph.
+constexpr int64_t kServeVertexBytes = 8 + 4 + 4 + 1 + 8 + 4 + 4 + 4 + 4;
+constexpr int64_t kServeEntryBytes = 4 + 4;
+
+kcore_status serve_arena_create(ServeArena* A, int device, int64_t nv, int64_t ne, int32_t max_slots,
+                                const kcore_tuning* tuning, void* stream);
+void serve_arena_destroy(ServeArena* A);
+// Slots already copied in (row offsets graph-local) join the next round.
+kcore_status serve_join(ServeArena* A, int32_t nslots, int64_t max_n, const int32_t pop[4], int32_t nhi,
+                        void* stream);
+// One step: `rounds` rounds over every resident graph, then the slots' activity words and the
+// control block are copied to the pinned host buffers.
+kcore_status serve_step(ServeArena* A, int32_t rounds, int32_t nslots, int32_t* host_status, void* host_ctl,
+                        void* stream);
+// Round base and error flag of a control block copied to the host.
+int32_t serve_ctl_rbase(const void* host_ctl);
+int32_t serve_ctl_error(const void* host_ctl);
+size_t serve_ctl_size();
 
 }  // namespace kcore

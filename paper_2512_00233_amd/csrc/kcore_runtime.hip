@@ -597,6 +597,150 @@ static kcore_status autotune_impl(int32_t G, const int64_t* gvo, const int64_t* 
   return KCORE_OK;
 }
 
+// ------------------------------------------------------------------ served graphs (device side)
+static Args<int64_t> serve_args(const ServeArena* A) {
+  Args<int64_t> a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = A->nv;
+  a.row_ptr = A->row_ptr;
+  a.col = A->col;
+  a.vbase = A->vbase;
+  a.est = A->est;
+  a.stamp = A->stamp;
+  a.cls = A->cls;
+  a.lists[0] = A->lists[0];
+  a.lists[1] = A->lists[1];
+  a.slist = nullptr;  // no first (all-vertex) round: graphs join through compaction rounds
+  a.pruned = A->pruned;
+  a.plen = A->plen;
+  a.plow = A->plow;
+  a.ctl = static_cast<Ctl*>(A->ctl);
+  a.tail_threshold = A->tu.tail;
+  a.list_cap = A->tu.list_cap;
+  a.one_sided = A->tu.one_sided;
+  a.prune = A->tu.prune;
+  a.gact = A->gact;
+  return a;
+}
+
+void serve_arena_destroy(ServeArena* A) {
+  if (A->step_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(A->step_exec));
+  A->step_exec = nullptr;
+  for (void* p : {(void*)A->row_ptr, (void*)A->est, (void*)A->stamp, (void*)A->cls, (void*)A->lists[0],
+                  (void*)A->lists[1], (void*)A->plen, (void*)A->plow, (void*)A->vbase, (void*)A->gact,
+                  (void*)A->col, (void*)A->pruned, A->ctl, A->slots, (void*)A->slot_vb, (void*)A->status})
+    if (p) (void)hipFree(p);
+  *A = ServeArena();
+}
+
+kcore_status serve_arena_create(ServeArena* A, int device, int64_t nv, int64_t ne, int32_t max_slots,
+                                const kcore_tuning* tuning, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  *A = ServeArena();
+  A->device = device;
+  hipDeviceProp_t prop;
+  KC_HIP(hipGetDeviceProperties(&prop, device));
+  A->num_cus = prop.multiProcessorCount;
+  A->nv = nv;
+  A->ne = std::max<int64_t>(ne, 1);
+  A->max_slots = max_slots;
+  A->tu = resolve_tuning(tuning, A->num_cus);
+  size_t bytes = 0;
+  auto alloc = [&](auto** p, size_t count) {
+    const size_t b = sizeof(**p) * std::max<size_t>(count, 1);
+    bytes += b;
+    return hipMalloc(reinterpret_cast<void**>(p), b) == hipSuccess;
+  };
+  const bool ok = alloc(&A->row_ptr, nv) && alloc(&A->est, nv) && alloc(&A->stamp, nv) && alloc(&A->cls, nv) &&
+                  alloc(&A->lists[0], nv) && alloc(&A->lists[1], nv) && alloc(&A->plen, nv) &&
+                  alloc(&A->plow, nv) && alloc(&A->vbase, nv) && alloc(&A->gact, nv) && alloc(&A->col, A->ne) &&
+                  alloc(&A->pruned, A->ne) && alloc(reinterpret_cast<Ctl**>(&A->ctl), 1) &&
+                  alloc(reinterpret_cast<SlotDesc**>(&A->slots), max_slots) && alloc(&A->slot_vb, max_slots) &&
+                  alloc(&A->status, max_slots);
+  if (!ok) {
+    (void)hipGetLastError();
+    serve_arena_destroy(A);
+    return fail(KCORE_E_NOMEM, "server arena allocation failed (" + std::to_string(bytes) + " bytes requested)");
+  }
+  A->bytes = bytes;
+  KC_HIP(hipMemsetAsync(A->stamp, 0, sizeof(int32_t) * nv, st));
+  KC_HIP(hipMemsetAsync(A->slot_vb, 0xff, sizeof(int32_t) * max_slots, st));
+  hipLaunchKernelGGL(k_serve_reset, dim3(1), dim3(256), 0, st, static_cast<Ctl*>(A->ctl), 2);
+  KC_HIP(hipGetLastError());
+  KC_HIP(hipStreamSynchronize(st));
+  return KCORE_OK;
+}
+
+kcore_status serve_join(ServeArena* A, int32_t nslots, int64_t max_n, const int32_t pop[4], int32_t nhi,
+                        void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const Args<int64_t> a = serve_args(A);
+  const SlotDesc* slots = static_cast<const SlotDesc*>(A->slots);
+  if (nslots > 0) {
+    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((max_n + kBlock) / kBlock, 64));
+    hipLaunchKernelGGL(k_slot_init<int64_t>, dim3(gx, nslots), dim3(kBlock), 0, st, a, slots, A->tu.t0, A->tu.t1,
+                       A->tu.t2);
+    hipLaunchKernelGGL(k_slot_shift, dim3(gx, nslots), dim3(kBlock), 0, st, A->row_ptr, slots);
+  }
+  hipLaunchKernelGGL(k_serve_join, dim3(1), dim3(64), 0, st, static_cast<Ctl*>(A->ctl), pop[0], pop[1], pop[2],
+                     pop[3], nhi);
+  KC_HIP(hipGetLastError());
+  return KCORE_OK;
+}
+
+kcore_status serve_step(ServeArena* A, int32_t rounds, int32_t nslots, int32_t* host_status, void* host_ctl,
+                        void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const Args<int64_t> a = serve_args(A);
+  const Tuning& tu = A->tu;
+  const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((A->nv + 4095) / 4096, (int64_t)A->num_cus * 8));
+  auto enqueue = [&]() {
+    for (int i = 0; i < rounds; ++i) {
+      hipLaunchKernelGGL((k_compact<false, int64_t>), dim3(cgrid), dim3(kBlock), 0, st, a, i);
+      hipLaunchKernelGGL((k_big<false, true, int64_t>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, i, 0);
+      hipLaunchKernelGGL((k_round<kBlock, false, true, int64_t>), dim3(tu.grid), dim3(kBlock), 0, st, a, i, 0);
+    }
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a.ctl, rounds);
+  };
+  if (!tu.use_graph) {
+    enqueue();
+    KC_HIP(hipGetLastError());
+  } else {
+    if (A->step_exec && A->step_rounds != rounds) {
+      (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(A->step_exec));
+      A->step_exec = nullptr;
+    }
+    if (!A->step_exec) {
+      hipGraph_t graph;
+      KC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      enqueue();
+      const hipError_t launch_err = hipGetLastError();
+      const hipError_t end_err = hipStreamEndCapture(st, &graph);
+      if (launch_err != hipSuccess) return hip_fail(launch_err, "step launch during capture");
+      if (end_err != hipSuccess) return hip_fail(end_err, "hipStreamEndCapture");
+      hipGraphExec_t exec;
+      const hipError_t inst_err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (inst_err != hipSuccess) return hip_fail(inst_err, "hipGraphInstantiate");
+      A->step_exec = exec;
+      A->step_rounds = rounds;
+    }
+    KC_HIP(hipGraphLaunch(static_cast<hipGraphExec_t>(A->step_exec), st));
+  }
+  if (nslots > 0) {
+    hipLaunchKernelGGL(k_slot_status, dim3((nslots + 255) / 256), dim3(256), 0, st, A->gact, A->slot_vb, nslots,
+                       A->status);
+    KC_HIP(hipGetLastError());
+    KC_HIP(hipMemcpyAsync(host_status, A->status, sizeof(int32_t) * nslots, hipMemcpyDeviceToHost, st));
+  }
+  KC_HIP(hipMemcpyAsync(host_ctl, A->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  return KCORE_OK;
+}
+
+int32_t serve_ctl_rbase(const void* host_ctl) { return static_cast<const Ctl*>(host_ctl)->rbase; }
+int32_t serve_ctl_error(const void* host_ctl) { return static_cast<const Ctl*>(host_ctl)->error; }
+size_t serve_ctl_size() { return sizeof(Ctl); }
+
 }  // namespace kcore
 
 using namespace kcore;

@@ -20,7 +20,9 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ["kcore_decompose", "kcore_decompose32", "kcore_decompose_batch", "kcore_last_error"]:
+    for required in ["kcore_decompose", "kcore_decompose32", "kcore_decompose_batch", "kcore_last_error",
+                     "kcore_serve_create", "kcore_serve_submit", "kcore_serve_poll", "kcore_serve_wait",
+                     "kcore_serve_stats", "kcore_serve_destroy"]:
         assert required in names
 
 
