@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ROOFLINE_RUNS = 3
 
 
 def algorithmic_bytes(updates, visits, changes, acts, off_bytes=8):
@@ -59,16 +60,28 @@ def measured_traffic(workload, kernel):
     return k.get("bytes_per_launch_scaled")
 
 
-def run_workload(name, steps, warmup, torch, kc, gg, want_stats=True):
+def kernel_bytes(k, off_bytes=8):
+    return algorithmic_bytes(k.vertex_updates, k.edge_visits, k.changes, k.activations, off_bytes)
+
+
+def run_workload(name, steps, warmup, torch, kc, gg, roofline_runs=3):
+    """Plain path on one resident graph: instrumented passes (per-kernel HIP events and
+    work counters, for the roofline), then `warmup` and `steps` timed decompositions."""
     g = gg.workload(name)
     dev = torch.device("cuda:0")
     rp = torch.from_numpy(g.row_ptr).to(dev)
     ci = torch.from_numpy(g.col_idx).to(dev)
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-    # statistics / per-kernel timing pass (not part of the timed region)
+    per_kernel = {k: {"bytes": 0, "ms": 0.0, "launches": 0} for k in kc.KERNELS}
     st = kc.Stats()
-    kc.decompose(rp, ci, out=out, tuning=kc.Tuning(timing=1), stats=st)
+    for _ in range(roofline_runs):
+        st = kc.Stats()
+        kc.decompose(rp, ci, out=out, tuning=kc.Tuning(timing=1), stats=st)
+        for i, k in enumerate(kc.KERNELS):
+            per_kernel[k]["bytes"] += kernel_bytes(st.kernel[i])
+            per_kernel[k]["ms"] += st.kernel[i].ms
+            per_kernel[k]["launches"] += st.kernel[i].launches
     for _ in range(warmup):
         kc.decompose(rp, ci, out=out)
     torch.cuda.synchronize()
@@ -82,7 +95,22 @@ def run_workload(name, steps, warmup, torch, kc, gg, want_stats=True):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - wall0) / steps * 1e3
     ms = t0.elapsed_time(t1) / steps
-    return g, out.cpu().numpy(), st, ms, wall
+    return g, out.cpu().numpy(), st, ms, wall, per_kernel
+
+
+def roofline_of(per_kernel, workload, kc, runs=ROOFLINE_RUNS):
+    """Dominant kernel (largest summed duration): algorithmic bytes per launch over its
+    average launch duration, against the HBM peak."""
+    name = max(per_kernel, key=lambda k: per_kernel[k]["ms"])
+    k = per_kernel[name]
+    launches = max(k["launches"], 1)
+    achieved = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
+    symbol = kc.KERNEL_SYMBOLS[name]
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, symbol),
+            "kernel": symbol, "launches_per_run": round(launches / max(1, runs)),
+            "bytes_per_launch": int(k["bytes"] / launches), "avg_launch_us": round(k["ms"] / launches * 1e3, 3),
+            "share_of_kernel_time": round(k["ms"] / max(1e-9, sum(v["ms"] for v in per_kernel.values())), 3)}
 
 
 def run_batch_workload(args, torch, kc, gg, np):
@@ -162,14 +190,135 @@ def run_batch_workload(args, torch, kc, gg, np):
     return res
 
 
+def run_serve_workload(args, torch, kc, gg, np):
+    """Served form: a seeded pool of graphs in pinned host memory, requests that
+    sample the pool; first a saturating burst (capacity), then Poisson arrivals
+    at a fraction of that capacity (latency), against FIFO plain calls (H2D,
+    kcore_decompose, D2H, one request at a time) on the same trace."""
+    import oracle
+    rng = np.random.default_rng(5)
+    t0 = time.perf_counter()
+    pool_b = gg.batch(args.pool, seed=6, nmin=1000, nmax=4_000_000)
+    pool = [pool_b.graph(i) for i in range(pool_b.num_graphs)]
+    gen_s = time.perf_counter() - t0
+    refs = [None] * len(pool)
+    ref_all = oracle.coreness_batch(pool_b.graph_vtx_off, pool_b.row_ptr, pool_b.col_idx,
+                                    threads=min(16, os.cpu_count() or 1))
+    for i in range(len(pool)):
+        refs[i] = ref_all[pool_b.graph_vtx_off[i]:pool_b.graph_vtx_off[i + 1]]
+    del pool_b, ref_all
+    pinned = [(torch.from_numpy(g.row_ptr).pin_memory(), torch.from_numpy(g.col_idx).pin_memory()) for g in pool]
+    N = args.requests
+    which = rng.integers(0, len(pool), N)
+    budget = args.serve_budget_gb << 30
+    wrong = 0
+
+    def serve_run(arrivals):
+        """Submit request j at arrivals[j] (seconds from start); returns (wall_s, stats)."""
+        nonlocal wrong
+        srv = kc.Server(hbm_budget_bytes=budget, max_queue=N + 16, rounds_per_step=args.rounds_per_step)
+        live = {}
+        start = time.perf_counter()
+
+        def drain():
+            nonlocal wrong
+            for c in srv.poll(1024):
+                j, out = live.pop(c.req_id)
+                if c.status != 0 or not np.array_equal(out.numpy(), refs[which[j]]):
+                    wrong += 1
+
+        for j in range(N):
+            while time.perf_counter() - start < arrivals[j]:
+                drain()
+            g = int(which[j])
+            out = torch.empty(pool[g].n, dtype=torch.int32, pin_memory=True)
+            rid = srv.submit(pinned[g][0], pinned[g][1], out)
+            live[rid] = (j, out)
+        while live:
+            drain()
+            time.sleep(0.0002)
+        wall = time.perf_counter() - start
+        st = srv.stats()
+        srv.close()
+        return wall, st
+
+    # warm-up (graph capture, allocator, first-touch of the pool)
+    wsrv = kc.Server(hbm_budget_bytes=budget, rounds_per_step=args.rounds_per_step)
+    for g in range(min(4, len(pool))):
+        o = torch.empty(pool[g].n, dtype=torch.int32, pin_memory=True)
+        wsrv.wait(wsrv.submit(pinned[g][0], pinned[g][1], o), timeout_s=120)
+    wsrv.close()
+    burst_wall, burst = serve_run(np.zeros(N))
+    capacity = burst["graphs_per_s"]
+    lam = args.load * capacity
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, N))
+    arrivals -= arrivals[0]
+    pois_wall, pois = serve_run(arrivals)
+
+    # FIFO baseline: the same Poisson trace served by one plain call at a time
+    dev = torch.device("cuda:0")
+    lat = []
+    start = time.perf_counter()
+    last_done = start
+    for j in range(N):
+        while time.perf_counter() - start < arrivals[j]:
+            pass
+        g = int(which[j])
+        rp = pinned[g][0].to(dev, non_blocking=True)
+        ci = pinned[g][1].to(dev, non_blocking=True)
+        out_d = kc.decompose(rp, ci)
+        out = torch.empty(pool[g].n, dtype=torch.int32, pin_memory=True)
+        out.copy_(out_d, non_blocking=True)
+        torch.cuda.synchronize()
+        last_done = time.perf_counter()
+        lat.append((last_done - start - arrivals[j]) * 1e6)
+        if not np.array_equal(out.numpy(), refs[g]):
+            wrong += 1
+    fifo_wall = last_done - start
+    lat = np.sort(np.array(lat))
+    fifo_rate = N / fifo_wall
+
+    def pct(a, q):
+        return float(a[min(len(a) - 1, int(np.ceil(q * len(a))) - 1)])
+
+    mean_n = float(np.mean([pool[int(g)].n for g in which]))
+    mean_nnz = float(np.mean([pool[int(g)].nnz for g in which]))
+    return {
+        "metric": "graphs/s and p50/p99 latency, served form (continuous batching) vs FIFO plain calls",
+        "value": round(capacity, 2),
+        "unit": "graphs/s",
+        "n_gpus": 1, "steps": N, "warmup": 4, "ms_per_step": round(burst_wall / N * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded pool of ER / Chung-Lu / lattice graphs, n log-uniform in [1e3, 4e6])",
+        "config": {"workload": "serve", "requests": N, "pool_graphs": len(pool), "mean_n": round(mean_n),
+                   "mean_entries": round(mean_nnz), "hbm_budget_gb": args.serve_budget_gb,
+                   "rounds_per_step": args.rounds_per_step, "generation_s": round(gen_s, 1)},
+        "saturated": {"graphs_per_s": round(capacity, 2), "p50_ms": round(burst["p50_us"] / 1e3, 3),
+                      "p99_ms": round(burst["p99_us"] / 1e3, 3), "peak_resident_gb": round(burst["bytes_peak"] / 2**30, 2),
+                      "steps": burst["steps"], "rounds": burst["rounds"]},
+        "poisson": {"load": args.load, "arrival_rate": round(lam, 2), "graphs_per_s": round(pois["graphs_per_s"], 2),
+                    "p50_ms": round(pois["p50_us"] / 1e3, 3), "p99_ms": round(pois["p99_us"] / 1e3, 3),
+                    "max_ms": round(pois["max_us"] / 1e3, 3)},
+        "fifo_plain": {"graphs_per_s": round(fifo_rate, 2), "p50_ms": round(pct(lat, 0.5) / 1e3, 3),
+                       "p99_ms": round(pct(lat, 0.99) / 1e3, 3), "max_ms": round(float(lat[-1]) / 1e3, 3)},
+        "speedup_vs_fifo": round(capacity / fifo_rate, 3),
+        "exact": wrong == 0,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat24",
-                    choices=["rmat24", "road", "er_small", "rmat20", "road_512", "batch"])
+                    choices=["rmat24", "road", "er_small", "rmat20", "road_512", "batch", "serve"])
     ap.add_argument("--graphs", type=int, default=2048, help="graphs in the batch workload")
+    ap.add_argument("--requests", type=int, default=2000, help="requests in the serve workload")
+    ap.add_argument("--pool", type=int, default=64, help="distinct graphs the serve requests sample")
+    ap.add_argument("--load", type=float, default=0.7, help="serve: Poisson arrival rate / saturated capacity")
+    ap.add_argument("--serve-budget-gb", type=int, default=64, help="serve: device arena budget (GiB)")
+    ap.add_argument("--rounds-per-step", type=int, default=8, help="serve: rounds between step boundaries")
     ap.add_argument("--autotune", default="", help="batch workload: run the autotuner and save to this JSON")
     ap.add_argument("--also", default="road,er_small", help="other plain workloads to report (comma list)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -193,28 +342,19 @@ def main():
     if args.workload == "batch":
         print(json.dumps(run_batch_workload(args, torch, kc, gg, np)), flush=True)
         return
+    if args.workload == "serve":
+        print(json.dumps(run_serve_workload(args, torch, kc, gg, np)), flush=True)
+        return
 
-    g, core, st, ms, wall = run_workload(args.workload, args.steps, args.warmup, torch, kc, gg)
+    g, core, st, ms, wall, per_kernel = run_workload(args.workload, args.steps, args.warmup, torch, kc, gg,
+                                                     ROOFLINE_RUNS)
     m_und = g.nnz // 2
     gteps = m_und / (ms * 1e-3) / 1e9
-
-    # roofline of the dominant round kernel
-    dense = dict(updates=st.dense_vertex_updates, visits=st.dense_edge_visits, changes=st.dense_changes,
-                 acts=st.dense_activations)
-    sparse = dict(updates=st.vertex_updates - dense["updates"], visits=st.edge_visits - dense["visits"],
-                  changes=st.changes - dense["changes"], acts=st.activations - dense["acts"])
-    kernels = {
-        "k_round<dense>": (algorithmic_bytes(**dense), st.dense_ms, 1),
-        "k_round<sparse>": (algorithmic_bytes(**sparse), st.sparse_ms, max(st.launches - 1, 1)),
-    }
-    kname = max(kernels, key=lambda k: kernels[k][1])
-    kbytes, kms, klaunches = kernels[kname]
-    achieved = (kbytes / klaunches) / ((kms / klaunches) * 1e-3) / 1e9 if kms > 0 else 0.0
-    traffic = measured_traffic(args.workload, kname)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
-                "launches": klaunches, "bytes_per_launch": int(kbytes / klaunches),
-                "avg_launch_ms": round(kms / klaunches, 5)}
+    roofline = roofline_of(per_kernel, args.workload, kc)
+    kernels = {kc.KERNEL_SYMBOLS[k]: {"ms_per_run": round(v["ms"] / ROOFLINE_RUNS, 4),
+                                      "launches_per_run": v["launches"] // ROOFLINE_RUNS,
+                                      "algorithmic_gb_per_run": round(v["bytes"] / ROOFLINE_RUNS / 1e9, 4)}
+               for k, v in per_kernel.items()}
 
     result = {
         "metric": "GTEPS to coreness fixpoint (plain kernel, one graph resident in HBM)",
@@ -233,13 +373,15 @@ def main():
                    "kmax": int(core.max()) if core.size else 0, "rounds": st.rounds, "tail_rounds": st.tail_rounds,
                    "edge_visits": st.edge_visits, "host_wall_ms_per_step": round(wall, 4)},
         "roofline": roofline,
+        "kernels": kernels,
     }
 
     also = []
     for name in [w for w in args.also.split(",") if w and w != args.workload]:
-        g2, _, st2, ms2, _ = run_workload(name, args.steps, args.warmup, torch, kc, gg)
+        g2, _, st2, ms2, _, pk2 = run_workload(name, args.steps, args.warmup, torch, kc, gg, 1)
         also.append({"workload": name, "value": round(g2.nnz / 2 / (ms2 * 1e-3) / 1e9, 3), "unit": "GTEPS",
-                     "ms_per_step": round(ms2, 4), "rounds": st2.rounds, "tail_rounds": st2.tail_rounds})
+                     "ms_per_step": round(ms2, 4), "rounds": st2.rounds, "tail_rounds": st2.tail_rounds,
+                     "roofline_frac": roofline_of(pk2, name, kc, 1)["frac"]})
     result["also"] = also
 
     if not args.no_cpu_baseline:

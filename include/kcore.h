@@ -59,7 +59,7 @@ typedef struct kcore_tuning {
   int32_t big_grid_blocks; /* workgroups per class-3 round launch (0: 4 per compute unit) */
   int32_t rounds_per_poll; /* rounds enqueued before the first host check of the frontier */
   int32_t activation;      /* 0: guarded two-sided rule (default), 1: one-sided rule */
-  int32_t timing;          /* 1: bracket every round launch with HIP events (fills the *_ms statistics) */
+  int32_t timing;          /* 1: bracket every kernel launch with HIP events (fills the ms statistics) */
   int32_t list_cap;        /* frontier list capacity per degree class; beyond it the next round rebuilds
                               its lists from the round stamps (0: library default 8192) */
   int32_t no_prune;        /* 1: disable the pruned adjacency (always scan the full neighbour list) */
@@ -67,27 +67,49 @@ typedef struct kcore_tuning {
   int32_t reserved[4];
 } kcore_tuning;
 
-/* Per-call statistics (optional output).  Edge visits count the adjacency
- * entries scanned by the h-index update. */
+/* Round kernels, as indices into kcore_stats.kernel.  The first round (every
+ * vertex of degree >= 2) runs its own instances of the class-3 and classes-0..2
+ * kernels; later rounds run a compaction kernel (list rebuild from the round
+ * stamps; it does nothing unless the previous round's lists overflowed), the
+ * class-3 kernel and the classes-0..2 kernel (which also hosts the
+ * single-workgroup tail). */
+enum {
+  KCORE_K_BIG_FIRST = 0,
+  KCORE_K_ROUND_FIRST = 1,
+  KCORE_K_BIG = 2,
+  KCORE_K_ROUND = 3,
+  KCORE_K_COMPACT = 4,
+  KCORE_K_COUNT = 5
+};
+
+/* Work and time of one round kernel over a call.  Edge visits count the
+ * adjacency entries scanned by the h-index update. */
+typedef struct kcore_kernel_stats {
+  int64_t launches;        /* launches of this kernel */
+  int64_t vertex_updates;  /* vertices whose h-index it recomputed */
+  int64_t edge_visits;     /* adjacency entries read by those recomputations */
+  int64_t changes;         /* estimate decreases */
+  int64_t activations;     /* vertices it put in a next frontier */
+  int64_t prune_writes;    /* entries it wrote to pruned neighbour lists */
+  int64_t full_scans;      /* recomputations that read the full neighbour list */
+  double ms;               /* summed launch durations (timing mode only: HIP events on the stream) */
+} kcore_kernel_stats;
+
+/* Per-call statistics (optional output). */
 typedef struct kcore_stats {
   int64_t rounds;          /* rounds until the frontier emptied (multi-workgroup + tail) */
   int64_t tail_rounds;     /* of which run inside the single-workgroup tail */
-  int64_t launches;        /* round-kernel launches */
-  int64_t vertex_updates;  /* vertices whose h-index was recomputed */
-  int64_t edge_visits;     /* adjacency entries read by those recomputations */
-  int64_t changes;         /* estimate decreases */
-  int64_t activations;     /* vertices appended to a next frontier */
-  /* first round (every vertex of degree >= 2) alone; filled only when tuning.timing == 1 */
-  int64_t dense_vertex_updates;
-  int64_t dense_edge_visits;
-  int64_t dense_changes;
-  int64_t dense_activations;
-  double dense_ms;         /* duration of the dense round kernel (timing mode) */
-  double sparse_ms;        /* summed durations of all later round kernels (timing mode) */
-  int64_t full_scans;      /* recomputations that read the full neighbour list */
-  int64_t prune_writes;    /* entries written to pruned neighbour lists */
+  int64_t launches;        /* rounds enqueued (each one launch of every later-round kernel) */
   int64_t dense_rounds;    /* rounds whose lists were rebuilt from the round stamps */
-  int64_t reserved2;
+  int64_t vertex_updates;  /* totals over the kernels */
+  int64_t edge_visits;
+  int64_t changes;
+  int64_t activations;
+  int64_t prune_writes;
+  int64_t full_scans;
+  double init_ms;          /* timing mode: estimate initialisation and first-round lists */
+  double total_ms;         /* timing mode: init_ms + every kernel's ms */
+  kcore_kernel_stats kernel[KCORE_K_COUNT];
 } kcore_stats;
 
 /*

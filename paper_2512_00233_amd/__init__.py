@@ -53,30 +53,56 @@ class Tuning(ctypes.Structure):
     ]
 
 
+KERNELS = ("big_first", "round_first", "big", "round", "compact")
+# rocprofv3 names of the kernels of a single-graph run (int64 offsets), by KERNELS entry
+KERNEL_SYMBOLS = {
+    "big_first": "k_big<true, false, long>",
+    "round_first": "k_round<256, true, false, long>",
+    "big": "k_big<false, false, long>",
+    "round": "k_round<256, false, false, long>",
+    "compact": "k_compact<false, long>",
+}
+
+
+class KernelStats(ctypes.Structure):
+    """Mirror of ``kcore_kernel_stats``."""
+    _fields_ = [
+        ("launches", ctypes.c_int64),
+        ("vertex_updates", ctypes.c_int64),
+        ("edge_visits", ctypes.c_int64),
+        ("changes", ctypes.c_int64),
+        ("activations", ctypes.c_int64),
+        ("prune_writes", ctypes.c_int64),
+        ("full_scans", ctypes.c_int64),
+        ("ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class Stats(ctypes.Structure):
     """Mirror of ``kcore_stats``."""
     _fields_ = [
         ("rounds", ctypes.c_int64),
         ("tail_rounds", ctypes.c_int64),
         ("launches", ctypes.c_int64),
+        ("dense_rounds", ctypes.c_int64),
         ("vertex_updates", ctypes.c_int64),
         ("edge_visits", ctypes.c_int64),
         ("changes", ctypes.c_int64),
         ("activations", ctypes.c_int64),
-        ("dense_vertex_updates", ctypes.c_int64),
-        ("dense_edge_visits", ctypes.c_int64),
-        ("dense_changes", ctypes.c_int64),
-        ("dense_activations", ctypes.c_int64),
-        ("dense_ms", ctypes.c_double),
-        ("sparse_ms", ctypes.c_double),
-        ("full_scans", ctypes.c_int64),
         ("prune_writes", ctypes.c_int64),
-        ("dense_rounds", ctypes.c_int64),
-        ("reserved2", ctypes.c_int64),
+        ("full_scans", ctypes.c_int64),
+        ("init_ms", ctypes.c_double),
+        ("total_ms", ctypes.c_double),
+        ("kernel", KernelStats * len(KERNELS)),
     ]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "kernel"}
+        d["kernels"] = {k: self.kernel[i].as_dict() for i, k in enumerate(KERNELS)}
+        return d
 
 
 class ServeConfig(ctypes.Structure):

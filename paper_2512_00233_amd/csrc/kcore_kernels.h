@@ -72,7 +72,8 @@ struct Ctl {
   int32_t tail_cnt[2][kClasses];  // counters of the single-workgroup tail
   int32_t pop[kClasses];          // vertices per degree class (list region sizes)
   int32_t seed_fill[kClasses];    // first-round (static) list sizes: vertices of degree >= 2 per class
-  unsigned long long stats[16];
+  unsigned long long stats[16];   // run counters (ST_ROUNDS ...)
+  unsigned long long kstats[4][6];  // per round kernel (KernelId): ST_UPDATES .. ST_FULL_SCANS
   int32_t error;                  // 1: the tail hit its round cap
   int32_t rbase;                  // round number of slot 0 of the next chunk of round launches
   int32_t tail_pending;           // rounds run by a tail since the last base advance (stamps up to rbase + this)
@@ -83,6 +84,8 @@ enum Stat {
   ST_TAIL_ROUNDS, ST_DENSE_ROUNDS
 };
 constexpr int kLaneStats = 6;  // stats accumulated per lane (ST_UPDATES .. ST_FULL_SCANS)
+// Round kernels whose work is counted separately (the first round's two, the later rounds' two).
+enum KernelId { KI_BIG_FIRST = 0, KI_ROUND_FIRST, KI_BIG, KI_ROUND, KI_COUNT };
 
 // Hard cap on rounds inside one tail invocation (a correct run needs far fewer;
 // the cap only guarantees that the kernel terminates).

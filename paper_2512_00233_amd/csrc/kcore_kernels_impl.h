@@ -799,7 +799,7 @@ __device__ __forceinline__ void upd_big_lite(const Args<Off>& a, const Sink& s, 
 
 // ------------------------------------------------------------------ statistics
 template <int BLOCK>
-__device__ __forceinline__ void flush_stats(Ctl* ctl, const LaneStats& st, unsigned long long* red64) {
+__device__ __forceinline__ void flush_stats(Ctl* ctl, int kid, const LaneStats& st, unsigned long long* red64) {
   constexpr int NW = BLOCK / kWave;
   const int wave = threadIdx.x / kWave;
 #pragma unroll
@@ -811,7 +811,7 @@ __device__ __forceinline__ void flush_stats(Ctl* ctl, const LaneStats& st, unsig
   if (threadIdx.x < kLaneStats) {
     unsigned long long t = 0;
     for (int w = 0; w < NW; ++w) t += red64[threadIdx.x * NW + w];
-    if (t) atomicAdd(&ctl->stats[threadIdx.x], t);
+    if (t) atomicAdd(&ctl->kstats[kid][threadIdx.x], t);
   }
 }
 
@@ -1050,14 +1050,14 @@ __global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t slot, int3
   if (!FIRST && !dense && f.n[3] == 0 && (int64_t)f.n[0] + 4ll * f.n[1] + 16ll * f.n[2] <= a.tail_threshold) {
     if (blockIdx.x == 0) {
       run_tail<BLOCK, BATCH>(a, round, f, st, red);
-      if (collect_stats) flush_stats<BLOCK>(ctl, st, red64);
+      if (collect_stats) flush_stats<BLOCK>(ctl, KI_ROUND, st, red64);
     }
     return;
   }
   const int nslot = (round + 1) % 3;
   const Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
   sweep_small<BLOCK, BATCH>(a, s, f, FIRST, round, blockIdx.x, gridDim.x, st);
-  if (collect_stats) flush_stats<BLOCK>(ctl, st, red64);
+  if (collect_stats) flush_stats<BLOCK>(ctl, FIRST ? KI_ROUND_FIRST : KI_ROUND, st, red64);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     atomicAdd(&ctl->stats[ST_ROUNDS], 1ull);
     if (dense) atomicAdd(&ctl->stats[ST_DENSE_ROUNDS], 1ull);
@@ -1083,7 +1083,7 @@ __global__ __launch_bounds__(kBigBlock) void k_big(Args<Off> a, int32_t slot, in
   const Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
   for (int32_t i = blockIdx.x; i < f.n[3]; i += gridDim.x)
     upd_big<BLOCK, BATCH>(a, s, f.list[f.b[3] + i], FIRST, round, st, red, hist);
-  if (collect_stats) flush_stats<BLOCK>(ctl, st, red64);
+  if (collect_stats) flush_stats<BLOCK>(ctl, FIRST ? KI_BIG_FIRST : KI_BIG, st, red64);
 }
 
 // Precondition check (only when requested): ids in range, no self-loops,

@@ -239,6 +239,27 @@ static kcore_status launch_chunk(Workspace* ws, const Args<Off>& a, const Tuning
   return KCORE_OK;
 }
 
+// Timing mode: one round with an event before and after each of its three
+// kernels (compaction, class 3, classes 0..2), then the base advance.
+template <bool BATCH, typename Off>
+static void launch_round_timed(const Args<Off>& a, const Tuning& tu, int cgrid, int32_t collect, hipEvent_t* ev,
+                               hipStream_t st) {
+  (void)hipEventRecord(ev[0], st);
+  hipLaunchKernelGGL((k_compact<false, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, 0);
+  (void)hipEventRecord(ev[1], st);
+  hipLaunchKernelGGL((k_big<false, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, 0, collect);
+  (void)hipEventRecord(ev[2], st);
+  hipLaunchKernelGGL((k_round<kBlock, false, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, 0, collect);
+  (void)hipEventRecord(ev[3], st);
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a.ctl, 1);
+}
+
+static float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, a, b);
+  return ms;
+}
+
 // Every vertex of every graph (one graph: vbase unused) to its fixpoint.
 // row_ptr holds global edge offsets; with BATCH, col holds graph-local ids.
 template <bool BATCH, typename Off>
@@ -270,41 +291,56 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   a.list_cap = tu.list_cap;
   a.one_sided = tu.one_sided;
   a.prune = tu.prune;
+  a.gact = nullptr;
   const int32_t collect = stats ? 1 : 0;
   const bool trace = env_flag("KCORE_TRACE");
   const bool timing = tu.timing || trace;
   const bool use_graph = tu.use_graph && !timing && st != nullptr;  // no capture on the null stream
   const int32_t r0 = ws->epoch;
-  double first_ms = 0, later_ms = 0;
-  unsigned long long first_st[4] = {0, 0, 0, 0};
+  double kms[KCORE_K_COUNT] = {0, 0, 0, 0, 0};
+  double init_ms = 0;
   if (timing) {
-    kcore_status s = ws->need_events(2 * 64);
+    kcore_status s = ws->need_events(4 * 64);
     if (s != KCORE_OK) return s;
   }
+  hipEvent_t* ev = timing ? ws->events.data() : nullptr;
+  if (timing) KC_HIP(hipEventRecord(ev[0], st));
   hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, st, ws->ctl);
   hipLaunchKernelGGL(k_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, r0, tu.t0, tu.t1, tu.t2);
   hipLaunchKernelGGL((k_compact<true, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, 0);
-  if (timing) KC_HIP(hipEventRecord(ws->events[0], st));
+  if (timing) KC_HIP(hipEventRecord(ev[1], st));
   hipLaunchKernelGGL((k_big<true, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, 0, collect);
+  if (timing) KC_HIP(hipEventRecord(ev[2], st));
   hipLaunchKernelGGL((k_round<kBlock, true, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, 0, collect);
+  if (timing) KC_HIP(hipEventRecord(ev[3], st));
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, ws->ctl, 1);
   KC_HIP(hipGetLastError());
-  unsigned long long prev_st[16];
+  unsigned long long prev[KI_COUNT][kLaneStats];
+  std::memset(prev, 0, sizeof(prev));
+  auto trace_line = [&](const Ctl& h, int32_t r, const char* what, float ms) {
+    unsigned long long d[kLaneStats] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < KI_COUNT; ++k)
+      for (int q = 0; q < kLaneStats; ++q) {
+        d[q] += h.kstats[k][q] - prev[k][q];
+        prev[k][q] = h.kstats[k][q];
+      }
+    std::fprintf(stderr, "[kcore-trace] %s round=%d front=%d/%d/%d/%d dense=%d updates=%llu visits=%llu "
+                 "changes=%llu acts=%llu pw=%llu full=%llu tail=%llu ms=%.3f\n", what, r - r0, h.cnt[r % 3][0],
+                 h.cnt[r % 3][1], h.cnt[r % 3][2], h.cnt[r % 3][3], h.overflow[r % 3][0], d[ST_UPDATES],
+                 d[ST_VISITS], d[ST_CHANGES], d[ST_ACTIVATIONS], d[ST_PRUNE_WRITES], d[ST_FULL_SCANS],
+                 h.stats[ST_TAIL_ROUNDS], ms);
+  };
   if (timing) {
-    KC_HIP(hipEventRecord(ws->events[1], st));
     KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     KC_HIP(hipStreamSynchronize(st));
-    float ms = 0;
-    KC_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
-    first_ms = ms;
-    for (int q = 0; q < 4; ++q) first_st[q] = ws->host_ctl->stats[ST_UPDATES + q];
-    std::memcpy(prev_st, ws->host_ctl->stats, sizeof(prev_st));
+    init_ms = elapsed(ev[0], ev[1]);
+    kms[KCORE_K_BIG_FIRST] = elapsed(ev[1], ev[2]);
+    kms[KCORE_K_ROUND_FIRST] = elapsed(ev[2], ev[3]);
     if (trace) {
-      const Ctl& h = *ws->host_ctl;
-      std::fprintf(stderr, "[kcore-trace] n=%lld nnz=%lld pop=%d/%d/%d/%d first visits=%llu updates=%llu "
-                   "changes=%llu acts=%llu ms=%.3f\n", (long long)n, (long long)nnz, h.pop[0], h.pop[1], h.pop[2],
-                   h.pop[3], prev_st[ST_VISITS], prev_st[ST_UPDATES], prev_st[ST_CHANGES], prev_st[ST_ACTIVATIONS],
-                   first_ms);
+      std::fprintf(stderr, "[kcore-trace] n=%lld nnz=%lld pop=%d/%d/%d/%d init_ms=%.3f\n", (long long)n,
+                   (long long)nnz, ws->host_ctl->pop[0], ws->host_ctl->pop[1], ws->host_ctl->pop[2],
+                   ws->host_ctl->pop[3], init_ms);
+      trace_line(*ws->host_ctl, r0 + 1, "first", (float)(kms[0] + kms[1]));
     }
   }
   int64_t launches = 1;
@@ -312,13 +348,8 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   int32_t r = r0 + 1;
   for (;;) {
     if (timing) {
-      for (int i = 0; i < K; ++i) {
-        // one round per event pair: launch the slot, then move the base by one
-        KC_HIP(hipEventRecord(ws->events[2 * i], st));
-        kcore_status s = launch_chunk<BATCH, Off>(ws, a, tu, cgrid, 1, collect, false, st);
-        if (s != KCORE_OK) return s;
-        KC_HIP(hipEventRecord(ws->events[2 * i + 1], st));
-      }
+      for (int i = 0; i < K; ++i) launch_round_timed<BATCH, Off>(a, tu, cgrid, collect, ev + 4 * i, st);
+      KC_HIP(hipGetLastError());
     } else {
       kcore_status s = launch_chunk<BATCH, Off>(ws, a, tu, cgrid, K, collect, use_graph, st);
       if (s != KCORE_OK) return s;
@@ -330,20 +361,11 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     r = h.rbase;
     if (timing) {
       for (int i = 0; i < K; ++i) {
-        float ms = 0;
-        KC_HIP(hipEventElapsedTime(&ms, ws->events[2 * i], ws->events[2 * i + 1]));
-        later_ms += ms;
-        if (trace) {
-          std::fprintf(stderr, "[kcore-trace] round=%d front=%d/%d/%d/%d dense=%d visits=%llu updates=%llu "
-                       "changes=%llu acts=%llu full=%llu pw=%llu tail=%llu ms=%.3f\n", r - 1 - r0,
-                       h.cnt[r % 3][0], h.cnt[r % 3][1], h.cnt[r % 3][2], h.cnt[r % 3][3], h.overflow[r % 3][0],
-                       h.stats[ST_VISITS] - prev_st[ST_VISITS], h.stats[ST_UPDATES] - prev_st[ST_UPDATES],
-                       h.stats[ST_CHANGES] - prev_st[ST_CHANGES], h.stats[ST_ACTIVATIONS] - prev_st[ST_ACTIVATIONS],
-                       h.stats[ST_FULL_SCANS] - prev_st[ST_FULL_SCANS],
-                       h.stats[ST_PRUNE_WRITES] - prev_st[ST_PRUNE_WRITES],
-                       h.stats[ST_TAIL_ROUNDS] - prev_st[ST_TAIL_ROUNDS], ms);
-          std::memcpy(prev_st, h.stats, sizeof(prev_st));
-        }
+        hipEvent_t* e = ev + 4 * i;
+        kms[KCORE_K_COMPACT] += elapsed(e[0], e[1]);
+        kms[KCORE_K_BIG] += elapsed(e[1], e[2]);
+        kms[KCORE_K_ROUND] += elapsed(e[2], e[3]);
+        if (trace) trace_line(h, r - 1, "", elapsed(e[0], e[3]));
       }
     }
     const int32_t* c = h.cnt[r % 3];
@@ -353,24 +375,36 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   }
   const Ctl& hc = *ws->host_ctl;
   if (hc.error) return fail(KCORE_E_HIP, "tail round cap reached (internal error)");
-  ws->epoch = r + (int32_t)hc.stats[ST_TAIL_ROUNDS] + 4;
+  ws->epoch = r + 4;  // the round base already counts the tail's rounds
   if (stats) {
     stats->rounds = (int64_t)hc.stats[ST_ROUNDS];
     stats->tail_rounds = (int64_t)hc.stats[ST_TAIL_ROUNDS];
     stats->launches = launches;
-    stats->vertex_updates = (int64_t)hc.stats[ST_UPDATES];
-    stats->edge_visits = (int64_t)hc.stats[ST_VISITS];
-    stats->changes = (int64_t)hc.stats[ST_CHANGES];
-    stats->activations = (int64_t)hc.stats[ST_ACTIVATIONS];
-    stats->dense_vertex_updates = (int64_t)first_st[0];
-    stats->dense_edge_visits = (int64_t)first_st[1];
-    stats->dense_changes = (int64_t)first_st[2];
-    stats->dense_activations = (int64_t)first_st[3];
-    stats->dense_ms = first_ms;
-    stats->sparse_ms = later_ms;
-    stats->full_scans = (int64_t)hc.stats[ST_FULL_SCANS];
-    stats->prune_writes = (int64_t)hc.stats[ST_PRUNE_WRITES];
     stats->dense_rounds = (int64_t)hc.stats[ST_DENSE_ROUNDS];
+    stats->init_ms = init_ms;
+    const int64_t kl[KCORE_K_COUNT] = {1, 1, launches - 1, launches - 1, launches - 1};
+    for (int k = 0; k < KCORE_K_COUNT; ++k) {
+      kcore_kernel_stats& o = stats->kernel[k];
+      o.launches = kl[k];
+      o.ms = kms[k];
+      if (k < KI_COUNT) {
+        const unsigned long long* q = hc.kstats[k];
+        o.vertex_updates = (int64_t)q[ST_UPDATES];
+        o.edge_visits = (int64_t)q[ST_VISITS];
+        o.changes = (int64_t)q[ST_CHANGES];
+        o.activations = (int64_t)q[ST_ACTIVATIONS];
+        o.prune_writes = (int64_t)q[ST_PRUNE_WRITES];
+        o.full_scans = (int64_t)q[ST_FULL_SCANS];
+        stats->vertex_updates += o.vertex_updates;
+        stats->edge_visits += o.edge_visits;
+        stats->changes += o.changes;
+        stats->activations += o.activations;
+        stats->prune_writes += o.prune_writes;
+        stats->full_scans += o.full_scans;
+      }
+      stats->total_ms += o.ms;
+    }
+    stats->total_ms += init_ms;
   }
   return KCORE_OK;
 }

@@ -52,3 +52,33 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(kc, "_LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         kc.load()
+
+
+def test_ctypes_mirrors_match_the_header(tmp_path):
+    """Every structure the binding mirrors has the header's size and field offsets (compiled with gcc)."""
+    import shutil
+    import subprocess
+    import paper_2512_00233_amd as kc
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    mirrors = {"kcore_tuning": kc.Tuning, "kcore_stats": kc.Stats, "kcore_kernel_stats": kc.KernelStats,
+               "kcore_serve_config": kc.ServeConfig, "kcore_completion": kc.Completion,
+               "kcore_serve_report": kc.ServeReport}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "kcore.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
