@@ -121,7 +121,7 @@ typedef struct kcore_stats {
  *             alias row_ptr or col_idx.  Used as the estimate array during the run.
  *   stream    hipStream_t (as void*), NULL for the default stream.
  * All graph buffers are owned by the caller and only read.  The library keeps
- * a per-device workspace (about 21 bytes per vertex plus 4 bytes per adjacency
+ * a per-device workspace (29 bytes per vertex plus 4 bytes per adjacency
  * entry for the pruned neighbour lists, and a small control block),
  * allocated on first use, grown on demand and reused by later calls.
  * Work is enqueued on `stream`; the call returns after the fixpoint has been
@@ -202,7 +202,7 @@ kcore_status kcore_tuning_cache_get(int32_t num_graphs, int64_t total_vertices, 
  * and stats may be called from any host thread.  No call on a server may be in
  * progress or made once kcore_serve_destroy has been called on it.
  */
-#define KCORE_SERVE_VERTEX_BYTES 41
+#define KCORE_SERVE_VERTEX_BYTES 45
 #define KCORE_SERVE_ENTRY_BYTES 8
 
 typedef struct kcore_serve_config {

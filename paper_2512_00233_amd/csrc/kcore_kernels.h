@@ -73,7 +73,9 @@ struct Ctl {
   int32_t pop[kClasses];          // vertices per degree class (list region sizes)
   int32_t seed_fill[kClasses];    // first-round (static) list sizes: vertices of degree >= 2 per class
   unsigned long long stats[16];   // run counters (ST_ROUNDS ...)
-  unsigned long long kstats[4][6];  // per round kernel (KernelId): ST_UPDATES .. ST_FULL_SCANS
+  // per round kernel (KernelId) and counter (ST_UPDATES .. ST_FULL_SCANS), spread over
+  // kStatCopies addresses by workgroup so that the flushes of a launch do not all meet
+  unsigned long long kstats[4][6][16];
   int32_t error;                  // 1: the tail hit its round cap
   int32_t rbase;                  // round number of slot 0 of the next chunk of round launches
   int32_t tail_pending;           // rounds run by a tail since the last base advance (stamps up to rbase + this)
@@ -84,6 +86,7 @@ enum Stat {
   ST_TAIL_ROUNDS, ST_DENSE_ROUNDS
 };
 constexpr int kLaneStats = 6;  // stats accumulated per lane (ST_UPDATES .. ST_FULL_SCANS)
+constexpr int kStatCopies = 16;
 // Round kernels whose work is counted separately (the first round's two, the later rounds' two).
 enum KernelId { KI_BIG_FIRST = 0, KI_ROUND_FIRST, KI_BIG, KI_ROUND, KI_COUNT };
 
@@ -110,6 +113,7 @@ struct Args {
   int32_t list_cap;    // sparse list capacity per class before overflow
   int32_t one_sided;
   int32_t prune;       // 0 disables the pruned adjacency
+  int32_t* slack;      // support at the own level minus the level, from the last recomputation
   int32_t* gact;       // served graphs: per graph (indexed by its base vertex) the last round it has work for
 };
 

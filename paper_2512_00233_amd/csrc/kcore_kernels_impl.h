@@ -75,33 +75,79 @@ __device__ __forceinline__ Sink make_sink(const Args<Off>& a, int32_t next_round
   return s;
 }
 
-// Activate up to N candidates per lane for the next round: deduplicate on the
-// round stamp (all atomics of a lane in flight together), then, unless the next
-// round already rebuilds its lists by compaction, append the winners to the
-// list of their degree class with one atomic per class per wavefront.  Every
-// active lane of the wavefront must call this.
-template <int N, typename Off>
-__device__ __forceinline__ void activate_batch(const Args<Off>& a, const Sink& s, const int32_t (&v)[N],
-                                               const bool (&want)[N], LaneStats& st, int32_t gb) {
-  bool anyw = false;
+// The current vertex dropped from e to h; up to N neighbours per lane (ids v,
+// estimates x read in this round, valid where `in`) are candidates for the
+// next round.  Neighbour v needs a recomputation only if the current vertex
+// was counted in v's support at v's level x (x <= e) and no longer is (x > h).
+// v keeps its support slack (support at its level minus the level, set when v
+// was last recomputed): the loss is subtracted, and v is activated only when
+// the slack goes negative.
+// A vertex of the current frontier is updated in this round too.  Class-3
+// vertices are updated by the class-3 kernel, which completes before the
+// classes-0..2 kernel of the same round starts (in the tail: before the small
+// classes, behind a barrier).  So, with BIG telling which kernel the current
+// vertex belongs to:
+//  * v updated by the same kernel may have read the old value of the current
+//    vertex, and x may be stale: v is re-activated;
+//  * v small, current vertex class 3: v is updated later and reads the new value;
+//  * v class 3, current vertex small: v's update is done, x is its new value and
+//    its slack counts the current vertex's old value: the exact rule applies.
+// A vertex already activated for the next round needs nothing.  In the first
+// round (dense) and in one-sided mode every candidate with x > h is activated.
+// Winners of the round-stamp dedup (atomicMax) are appended to the list of
+// their degree class with one atomic per class per wavefront, unless the next
+// round already rebuilds its lists by compaction.  Loads and atomics of a lane
+// are issued together at each step.  Every active lane of the wavefront must
+// call this.
+template <int N, bool BIG, typename Off>
+__device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink& s, int32_t (&v)[N],
+                                                 const int32_t (&x)[N], const bool (&in)[N], int32_t e, int32_t h,
+                                                 bool dense, int32_t round, LaneStats& st, int32_t gb) {
+  bool cand[N];
+  bool any = false;
 #pragma unroll
-  for (int i = 0; i < N; ++i) anyw |= want[i];
-  if (!ballot(anyw)) return;
+  for (int i = 0; i < N; ++i) {
+    cand[i] = in[i] && x[i] > h;
+    any |= cand[i];
+  }
+  if (!ballot(any)) return;
+  int32_t sv[N], cv[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) sv[i] = cand[i] ? a.stamp[v[i]] : INT32_MAX;
+  const bool always = a.one_sided || dense;
+  // the class is needed for frontier members (which kernel updates them) and for winners
+#pragma unroll
+  for (int i = 0; i < N; ++i) cv[i] = (!always && cand[i] && sv[i] == round) ? (int32_t)a.cls[v[i]] : -1;
+  uint32_t want = 0, sub = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (!cand[i] || sv[i] >= s.stamp) continue;  // not a candidate, or already in the next frontier
+    bool w = false, d = false;
+    if (always) w = true;
+    else if (sv[i] == round && (cv[i] == 3) == BIG) w = true;
+    else if (sv[i] == round && BIG) w = false;
+    else if (x[i] <= e) d = true;
+    want |= (w ? 1u : 0u) << i;
+    sub |= (d ? 1u : 0u) << i;
+  }
   int32_t p[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) p[i] = want[i] ? a.stamp[v[i]] : INT32_MAX;
+  for (int i = 0; i < N; ++i) p[i] = (sub >> i & 1u) ? atomicSub(&a.slack[v[i]], 1) : 1;
 #pragma unroll
-  for (int i = 0; i < N; ++i) p[i] = (p[i] < s.stamp) ? atomicMax(&a.stamp[v[i]], s.stamp) : INT32_MAX;
+  for (int i = 0; i < N; ++i) want |= ((sub >> i & 1u) && p[i] <= 0 ? 1u : 0u) << i;
+#pragma unroll
+  for (int i = 0; i < N; ++i) p[i] = (want >> i & 1u) ? atomicMax(&a.stamp[v[i]], s.stamp) : INT32_MAX;
   uint32_t first = 0;
 #pragma unroll
   for (int i = 0; i < N; ++i) first |= (p[i] < s.stamp ? 1u : 0u) << i;
   st.v[ST_ACTIVATIONS] += __popc(first);
-  // served graphs: the graph has work in the next round (all candidates share the activating vertex's graph)
+  // served graphs: the graph has work in the next round (all candidates share the current vertex's graph)
   if (a.gact && first) a.gact[gb] = s.stamp;
   const bool compact_next = s.overflow && *(volatile int32_t*)s.overflow;
   if (compact_next || !ballot(first != 0)) return;
 #pragma unroll
-  for (int i = 0; i < N; ++i) p[i] = (first >> i & 1u) ? (int32_t)a.cls[v[i]] : kClasses;  // class of winners
+  for (int i = 0; i < N; ++i)
+    p[i] = (first >> i & 1u) ? (cv[i] >= 0 ? cv[i] : (int32_t)a.cls[v[i]]) : kClasses;  // class of winners
   const int lane = lane_id();
 #pragma unroll
   for (int k = 0; k < kClasses; ++k) {
@@ -126,28 +172,20 @@ __device__ __forceinline__ void activate_batch(const Args<Off>& a, const Sink& s
   }
 }
 
-// Should neighbour v, whose estimate read in this round is x, be activated
-// after the current vertex dropped from e to h?
-template <typename Off>
-__device__ __forceinline__ bool decide(const Args<Off>& a, int32_t v, int32_t x, int32_t e, int32_t h, bool dense,
-                                       int32_t round) {
-  if (x <= h) return false;
-  if (a.one_sided || x <= e || dense) return true;
-  return a.stamp[v] == round;  // in the current frontier (its value may still move) and not yet re-activated
-}
-
 // ------------------------------------------------------------------ k-ary search over register values
 // Each group of G lanes holds R values per lane.  Returns, per group, the
-// largest k in [lo, e] with |{values >= k}| >= k, or lo - 1 when that count at
-// lo is below lo (possible only when the caller does not know count(lo) >= lo).
+// largest k in [lo, e] with |{values >= k}| >= k (and that count in `count`),
+// or lo - 1 when the count at lo is below lo (possible only when the caller
+// does not know count(lo) >= lo).
 // Pass 1 tests e, e-1, e-3, e-7, ..., lo; later passes cut the remaining
 // interval into kKary pieces.  Every lane of the wavefront must call this.
 template <int G, int R>
-__device__ __forceinline__ int32_t kary_regs(const int32_t (&x)[R], int32_t e, int32_t lo, bool active) {
+__device__ __forceinline__ int32_t kary_regs(const int32_t (&x)[R], int32_t e, int32_t lo, bool active,
+                                             int32_t& count) {
   constexpr int S = kKary;
   const int lane = lane_id();
   const uint64_t gm = (G == kWave) ? ~0ull : (((1ull << G) - 1) << (lane & ~(G - 1)));
-  int32_t hi = e, res = lo - 1;
+  int32_t hi = e, res = lo - 1, clo = 0;
   bool done = !active, first = true;
   while (ballot(!done)) {
     int32_t t[S];
@@ -177,15 +215,17 @@ __device__ __forceinline__ int32_t kary_regs(const int32_t (&x)[R], int32_t e, i
         if (qs < 0) {
           done = true;
         } else {
-          int32_t nhi = e, nlo = t[0];
+          int32_t nhi = e, nlo = t[0], nc = c[0];
 #pragma unroll
           for (int q = 1; q < S; ++q)
             if (q == qs) {
               nhi = t[q - 1] - 1;
               nlo = t[q];
+              nc = c[q];
             }
           lo = nlo;
           hi = nhi;
+          clo = nc;
         }
         first = false;
       } else {
@@ -196,14 +236,18 @@ __device__ __forceinline__ int32_t kary_regs(const int32_t (&x)[R], int32_t e, i
         if (qs < 0) {
           hi = t[0] - 1;
         } else {
-          int32_t nlo = t[0], nhi = hi;
+          int32_t nlo = t[0], nhi = hi, nc = c[0];
 #pragma unroll
           for (int q = 0; q < S; ++q) {
-            if (q == qs) nlo = t[q];
+            if (q == qs) {
+              nlo = t[q];
+              nc = c[q];
+            }
             if (q == qs + 1) nhi = t[q] - 1;
           }
           lo = nlo;
           hi = nhi;
+          clo = nc;
         }
       }
       if (!done && lo >= hi) {
@@ -212,6 +256,7 @@ __device__ __forceinline__ int32_t kary_regs(const int32_t (&x)[R], int32_t e, i
       }
     }
   }
+  count = clo;
   return res;
 }
 
@@ -242,25 +287,27 @@ __device__ __forceinline__ void upd_lane(const Args<Off>& a, const Sink& s, int3
     for (int i = 0; i < kLaneMaxDeg; ++i) cnt += x[i] >= e;
     if (cnt < e) {
       h = 1;
+      cnt = d;  // every neighbour of a vertex of degree >= 1 has an estimate >= 1
       for (int k = e - 1; k >= 2; --k) {
         int sk = 0;
 #pragma unroll
         for (int i = 0; i < kLaneMaxDeg; ++i) sk += x[i] >= k;
         if (sk >= k) {
           h = k;
+          cnt = sk;
           break;
         }
       }
       a.est[u] = h;
       st.v[ST_CHANGES] += 1;
     }
+    a.slack[u] = cnt - h;
   }
   const bool changed = valid && h < e;
-  if (!ballot(changed)) return;
-  bool w[kLaneMaxDeg];
+  bool in[kLaneMaxDeg];
 #pragma unroll
-  for (int i = 0; i < kLaneMaxDeg; ++i) w[i] = changed && i < d && decide(a, c[i], x[i], e, h, dense, round);
-  activate_batch<kLaneMaxDeg>(a, s, c, w, st, gb);
+  for (int i = 0; i < kLaneMaxDeg; ++i) in[i] = changed && i < d;
+  activate_changed<kLaneMaxDeg, false>(a, s, c, x, in, e, h, dense, round, st, gb);
 }
 
 // ------------------------------------------------------------------ class 1: 16-lane group per vertex
@@ -290,17 +337,18 @@ __device__ __forceinline__ void upd_group(const Args<Off>& a, const Sink& s, int
     st.v[ST_UPDATES] += 1;
     st.v[ST_VISITS] += (uint64_t)d;
   }
-  const int32_t h = kary_regs<G, R>(x, e, 1, valid);
+  int32_t cnt = 0;
+  const int32_t h = kary_regs<G, R>(x, e, 1, valid, cnt);
   const bool changed = valid && h < e;
   if (changed && gl == 0) {
     a.est[u] = h;
     st.v[ST_CHANGES] += 1;
   }
-  if (!ballot(changed)) return;
-  bool w[R];
+  if (valid && gl == 0) a.slack[u] = cnt - h;
+  bool in[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) w[r] = changed && (gl + G * r < d) && decide(a, c[r], x[r], e, h, dense, round);
-  activate_batch<R>(a, s, c, w, st, gb);
+  for (int r = 0; r < R; ++r) in[r] = changed && (gl + G * r < d);
+  activate_changed<R, false>(a, s, c, x, in, e, h, dense, round, st, gb);
 }
 
 // ------------------------------------------------------------------ class 2: wavefront per vertex
@@ -333,11 +381,11 @@ __device__ __forceinline__ void upd_wave(const Args<Off>& a, const Sink& s, int3
     }
   };
   if (lane == 0) st.v[ST_UPDATES] += 1;
-  int32_t h = -1;
+  int32_t h = -1, cnt = 0;
   if (pl > 0) {
     load(a.pruned, pl, 0);
     if (lane == 0) st.v[ST_VISITS] += pl;
-    const int32_t hp = kary_regs<kWave, R>(x, e, L, true);
+    const int32_t hp = kary_regs<kWave, R>(x, e, L, true, cnt);
     if (hp >= L) h = hp;
   }
   if (h < 0) {
@@ -346,7 +394,7 @@ __device__ __forceinline__ void upd_wave(const Args<Off>& a, const Sink& s, int3
       st.v[ST_VISITS] += d;
       st.v[ST_FULL_SCANS] += 1;
     }
-    h = kary_regs<kWave, R>(x, e, 1, true);
+    h = kary_regs<kWave, R>(x, e, 1, true, cnt);
     if (a.prune) {
       const int32_t L2 = max(2, (3 * h) / 4);
       int32_t off = 0;
@@ -366,15 +414,16 @@ __device__ __forceinline__ void upd_wave(const Args<Off>& a, const Sink& s, int3
       }
     }
   }
+  if (lane == 0) a.slack[u] = cnt - h;
   if (h == e) return;
   if (lane == 0) {
     a.est[u] = h;
     st.v[ST_CHANGES] += 1;
   }
-  bool w[R];
+  bool in[R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) w[i] = (lane + kWave * i < len) && decide(a, c[i], x[i], e, h, dense, round);
-  activate_batch<R>(a, s, c, w, st, gb);
+  for (int i = 0; i < R; ++i) in[i] = lane + kWave * i < len;
+  activate_changed<R, false>(a, s, c, x, in, e, h, dense, round, st, gb);
 }
 
 // ------------------------------------------------------------------ class 3: workgroup per vertex
@@ -412,11 +461,12 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t& total, in
 // Workgroup version of kary_regs (the whole workgroup is one group); red holds
 // kKary * (BLOCK / 64) ints.
 template <int BLOCK, int R>
-__device__ __forceinline__ int32_t kary_block(const int32_t (&x)[R], int32_t e, int32_t lo, int32_t* red) {
+__device__ __forceinline__ int32_t kary_block(const int32_t (&x)[R], int32_t e, int32_t lo, int32_t* red,
+                                              int32_t& count) {
   constexpr int S = kKary;
   constexpr int NW = BLOCK / kWave;
   const int wave = threadIdx.x / kWave;
-  int32_t hi = e;
+  int32_t hi = e, clo = 0;
   bool first = true;
   for (;;) {
     int32_t t[S];
@@ -453,15 +503,17 @@ __device__ __forceinline__ int32_t kary_block(const int32_t (&x)[R], int32_t e, 
       for (int q = S - 1; q >= 0; --q)
         if (c[q] >= t[q]) qs = q;
       if (qs < 0) return lo - 1;
-      int32_t nhi = e, nlo = t[0];
+      int32_t nhi = e, nlo = t[0], nc = c[0];
 #pragma unroll
       for (int q = 1; q < S; ++q)
         if (q == qs) {
           nhi = t[q - 1] - 1;
           nlo = t[q];
+          nc = c[q];
         }
       lo = nlo;
       hi = nhi;
+      clo = nc;
       first = false;
     } else {
       int qs = -1;
@@ -471,30 +523,39 @@ __device__ __forceinline__ int32_t kary_block(const int32_t (&x)[R], int32_t e, 
       if (qs < 0) {
         hi = t[0] - 1;
       } else {
-        int32_t nlo = t[0], nhi = hi;
+        int32_t nlo = t[0], nhi = hi, nc = c[0];
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-          if (q == qs) nlo = t[q];
+          if (q == qs) {
+            nlo = t[q];
+            nc = c[q];
+          }
           if (q == qs + 1) nhi = t[q] - 1;
         }
         lo = nlo;
         hi = nhi;
+        clo = nc;
       }
     }
-    if (lo >= hi) return lo;
+    if (lo >= hi) {
+      count = clo;
+      return lo;
+    }
   }
 }
 
 // Workgroup-wide search over a list in global memory, re-read on each pass:
-// the largest k in [lo, hi] with count(k) >= k, or lo - 1 when count(lo) < lo.
+// the largest k in [lo, hi] with count(k) >= k (and that count), or lo - 1
+// when count(lo) < lo.
 // Each pass tests kKary thresholds (used only for cores above kHistBins).
 template <int BLOCK, typename Off>
 __device__ __forceinline__ int32_t mp_search(const Args<Off>& a, const int32_t* src, int32_t off, int32_t len,
-                                             int32_t lo, int32_t hi, int32_t* red) {
+                                             int32_t lo, int32_t hi, int32_t* red, int32_t& count) {
   constexpr int S = kKary;
   constexpr int NW = BLOCK / kWave;
   const int tid = threadIdx.x;
   bool lo_known = false;
+  int32_t clo = 0;
   while (!(lo_known && lo >= hi)) {
     const int first = lo_known ? 0 : 1;
     const int slots = S - first;
@@ -521,16 +582,20 @@ __device__ __forceinline__ int32_t mp_search(const Args<Off>& a, const int32_t* 
       if (lane_id() == 0) red[q * NW + wave] = w;
     }
     __syncthreads();
-    int32_t best = -1;
+    int32_t best = -1, cbest = 0;
 #pragma unroll
     for (int q = 0; q < S; ++q) {
       int32_t tot = 0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) tot += red[q * NW + w];
-      if (t[q] != INT32_MAX && tot >= t[q]) best = q;  // count(k) - k is decreasing: the hits form a prefix
+      if (t[q] != INT32_MAX && tot >= t[q]) {  // count(k) - k is decreasing: the hits form a prefix
+        best = q;
+        cbest = tot;
+      }
     }
     __syncthreads();
     best = uni(best);
+    cbest = uni(cbest);
     if (!lo_known) {
       if (best < 0) return lo - 1;
       lo_known = true;
@@ -546,8 +611,10 @@ __device__ __forceinline__ int32_t mp_search(const Args<Off>& a, const int32_t* 
       }
       lo = nlo;
       hi = nhi;
+      clo = cbest;
     }
   }
+  count = clo;
   return lo;
 }
 
@@ -557,8 +624,8 @@ __device__ __forceinline__ int32_t mp_search(const Args<Off>& a, const int32_t* 
 // answer lies above top, the multi-pass search finishes over (top, e].
 template <int BLOCK, typename Off>
 __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t* src, int32_t off, int32_t len,
-                                               int32_t lo, int32_t e, int32_t* red, int32_t* hist) {
-  constexpr int U = 4;  // loads in flight per thread
+                                               int32_t lo, int32_t e, int32_t* red, int32_t* hist, int32_t& count) {
+  constexpr int U = 8;  // loads in flight per thread
   const int tid = threadIdx.x;
   const int32_t top = (int32_t)min((int64_t)e, (int64_t)lo + kHistBins - 1);
   const int32_t nb = top - lo + 1;
@@ -589,26 +656,34 @@ __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t
   int32_t total = 0;
   const int32_t before = block_excl_scan<BLOCK>(local, total, red);
   int32_t run = tot_above + (total - before - local);  // values above my bins
-  int32_t cand = -1;
+  // candidate and its count, packed so that the maximum picks the largest candidate
+  long long cand = -1;
   for (int32_t b = b1 - 1; b >= b0; --b) {
     run += hist[b];
     if (run >= lo + b) {
-      cand = lo + b;
+      cand = ((long long)b << 32) | (unsigned)run;
       break;
     }
   }
-  int32_t wm = cand;
+  long long wm = cand;
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) wm = max(wm, __shfl_xor(wm, o));
+  for (int o = 32; o >= 1; o >>= 1) {
+    const long long other = __shfl_xor(wm, o);
+    wm = other > wm ? other : wm;
+  }
   const int wave = tid / kWave;
-  if (lane_id() == 0) red[wave] = wm;
+  long long* red64 = reinterpret_cast<long long*>(hist);  // bins are no longer needed
   __syncthreads();
-  int32_t best = -1;
+  if (lane_id() == 0) red64[wave] = wm;
+  __syncthreads();
+  long long best = -1;
 #pragma unroll
-  for (int w = 0; w < BLOCK / kWave; ++w) best = max(best, red[w]);
+  for (int w = 0; w < BLOCK / kWave; ++w) best = red64[w] > best ? red64[w] : best;
   __syncthreads();
-  if (top < e && tot_above >= top + 1) return mp_search<BLOCK>(a, src, off, len, top + 1, e, red);
-  return best >= lo ? best : lo - 1;
+  if (top < e && tot_above >= top + 1) return mp_search<BLOCK>(a, src, off, len, top + 1, e, red, count);
+  if (best < 0) return lo - 1;
+  count = (int32_t)(best & 0xffffffffll);
+  return lo + (int32_t)(best >> 32);
 }
 
 // One workgroup per vertex of class 3.  Lists of up to BLOCK * kBigRegs entries
@@ -647,20 +722,20 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
     }
   };
   if (tid == 0) st.v[ST_UPDATES] += 1;
-  int32_t h = -1;
+  int32_t h = -1, cnt = 0;
   if (pl > 0) {
     if (tid == 0) st.v[ST_VISITS] += pl;
     if (pl <= CAPR) {
       load(a.pruned, pl, 0);
       inreg = true;
-      const int32_t hp = kary_block<BLOCK, R>(x, e, L, red);
+      const int32_t hp = kary_block<BLOCK, R>(x, e, L, red, cnt);
       if (hp >= L) h = hp;
     } else {
       inreg = false;
       len = pl;
       src = a.pruned;
       soff = 0;
-      const int32_t hp = hist_search<BLOCK>(a, a.pruned + beg, 0, pl, L, e, red, hist);
+      const int32_t hp = hist_search<BLOCK>(a, a.pruned + beg, 0, pl, L, e, red, hist, cnt);
       if (hp >= L) h = hp;
     }
   }
@@ -673,7 +748,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
     if (d <= CAPR) {
       load(a.col, d, gb);
       inreg = true;
-      h = kary_block<BLOCK, R>(x, e, 1, red);
+      h = kary_block<BLOCK, R>(x, e, 1, red, cnt);
       if (a.prune) {
         const int32_t L2 = max(2, (3 * h) / 4);
         int32_t mine = 0;
@@ -695,10 +770,11 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
       len = d;
       src = a.col;
       soff = gb;
-      h = hist_search<BLOCK>(a, a.col + beg, gb, d, 1, e, red, hist);
+      h = hist_search<BLOCK>(a, a.col + beg, gb, d, 1, e, red, hist, cnt);
       rebuild_pass = a.prune != 0;
     }
   }
+  if (tid == 0) a.slack[u] = cnt - h;
   const bool changed = h < e;
   if (!changed && !rebuild_pass) return;
   if (changed && tid == 0) {
@@ -706,33 +782,45 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
     st.v[ST_CHANGES] += 1;
   }
   if (inreg) {
-    bool w[R];
+    bool in[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) w[i] = (tid + BLOCK * i < len) && decide(a, c[i], x[i], e, h, dense, round);
-    activate_batch<R>(a, s, c, w, st, gb);
+    for (int i = 0; i < R; ++i) in[i] = tid + BLOCK * i < len;
+    activate_changed<R, true>(a, s, c, x, in, e, h, dense, round, st, gb);
     return;
   }
-  // streaming pass over the list: activation and/or rebuilding the pruned list
+  // streaming pass over the list, U entries per thread at a time: activation
+  // and/or rebuilding the pruned list (one workgroup scan per U * BLOCK entries)
+  constexpr int U = 8;
   const int32_t L2 = max(2, (3 * h) / 4);
   int32_t written = 0;
-  for (int32_t j0 = 0; j0 < len; j0 += BLOCK) {
-    const int32_t j = j0 + tid;
-    int32_t v[1] = {0};
-    int32_t xv = 0;
-    if (j < len) {
-      v[0] = soff + src[beg + j];
-      xv = a.est[v[0]];
+  for (int32_t j0 = 0; j0 < len; j0 += BLOCK * U) {
+    int32_t v[U], xv[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int32_t j = j0 + q * BLOCK + tid;
+      v[q] = j < len ? soff + src[beg + j] : -1;
     }
+#pragma unroll
+    for (int q = 0; q < U; ++q) xv[q] = v[q] >= 0 ? a.est[v[q]] : 0;
     if (rebuild_pass) {
-      const int32_t keep = (j < len) && xv >= L2;
+      int32_t mine = 0;
+#pragma unroll
+      for (int q = 0; q < U; ++q) mine += v[q] >= 0 && xv[q] >= L2;
       int32_t total = 0;
-      const int32_t off = block_excl_scan<BLOCK>(keep, total, red);
-      if (keep) a.pruned[beg + written + off] = v[0];
+      int32_t off = block_excl_scan<BLOCK>(mine, total, red);
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+        if (v[q] >= 0 && xv[q] >= L2) a.pruned[beg + written + off++] = v[q];
       written += total;
     }
     if (changed) {
-      bool w[1] = {(j < len) && decide(a, v[0], xv, e, h, dense, round)};
-      activate_batch<1>(a, s, v, w, st, gb);
+      bool in[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        in[q] = v[q] >= 0;
+        v[q] = max(v[q], 0);
+      }
+      activate_changed<U, true>(a, s, v, xv, in, e, h, dense, round, st, gb);
     }
   }
   if (rebuild_pass && tid == 0) {
@@ -758,12 +846,12 @@ __device__ __forceinline__ void upd_big_lite(const Args<Off>& a, const Sink& s, 
   const int32_t pl = a.prune ? uni(a.plen[u]) : 0;
   const int32_t L = pl > 0 ? uni(a.plow[u]) : 1;
   if (tid == 0) st.v[ST_UPDATES] += 1;
-  int32_t h = -1;
+  int32_t h = -1, cnt = 0;
   const int32_t* src = a.col + beg;
   int32_t len = d, off = gb;
   if (pl > 0) {
     if (tid == 0) st.v[ST_VISITS] += pl;
-    h = mp_search<BLOCK>(a, a.pruned + beg, 0, pl, L, e, red);
+    h = mp_search<BLOCK>(a, a.pruned + beg, 0, pl, L, e, red, cnt);
     if (h >= L) {
       src = a.pruned + beg;
       len = pl;
@@ -778,8 +866,9 @@ __device__ __forceinline__ void upd_big_lite(const Args<Off>& a, const Sink& s, 
       st.v[ST_FULL_SCANS] += 1;
       if (pl > 0) a.plen[u] = 0;
     }
-    h = mp_search<BLOCK>(a, a.col + beg, gb, d, 1, e, red);
+    h = mp_search<BLOCK>(a, a.col + beg, gb, d, 1, e, red, cnt);
   }
+  if (tid == 0) a.slack[u] = cnt - h;
   if (h == e) return;
   if (tid == 0) {
     a.est[u] = h;
@@ -787,13 +876,13 @@ __device__ __forceinline__ void upd_big_lite(const Args<Off>& a, const Sink& s, 
   }
   for (int32_t j0 = 0; j0 < len; j0 += BLOCK) {
     const int32_t j = j0 + tid;
-    int32_t v[1] = {0};
-    bool w[1] = {false};
-    if (j < len) {
+    int32_t v[1] = {0}, xv[1] = {0};
+    bool in[1] = {j < len};
+    if (in[0]) {
       v[0] = off + src[j];
-      w[0] = decide(a, v[0], a.est[v[0]], e, h, false, round);
+      xv[0] = a.est[v[0]];
     }
-    activate_batch<1>(a, s, v, w, st, gb);
+    activate_changed<1, true>(a, s, v, xv, in, e, h, false, round, st, gb);
   }
 }
 
@@ -811,7 +900,7 @@ __device__ __forceinline__ void flush_stats(Ctl* ctl, int kid, const LaneStats& 
   if (threadIdx.x < kLaneStats) {
     unsigned long long t = 0;
     for (int w = 0; w < NW; ++w) t += red64[threadIdx.x * NW + w];
-    if (t) atomicAdd(&ctl->kstats[kid][threadIdx.x], t);
+    if (t) atomicAdd(&ctl->kstats[kid][threadIdx.x][blockIdx.x % kStatCopies], t);
   }
 }
 
@@ -890,6 +979,7 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
     }
     const Sink s = make_sink(a, r + 1, ctl->tail_cnt[(t + 1) & 1], nullptr, false);
     for (int32_t i = 0; i < f.n[3]; ++i) upd_big_lite<BLOCK, BATCH>(a, s, f.list[f.b[3] + i], r, st, red);
+    __syncthreads();  // class-3 updates of this round are visible before the small classes run
     sweep_small<BLOCK, BATCH>(a, s, f, false, r, 0, 1, st);
     __syncthreads();
     if (t > 0 && tid < kClasses) ctl->tail_cnt[t & 1][tid] = 0;  // reused by round t+2
@@ -1067,12 +1157,15 @@ __global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t slot, int3
 // One round, class 3 (degree above the wavefront class): one workgroup per
 // vertex.  Runs before k_round of the same round; a round handed to the tail
 // has no class-3 vertex, so this kernel then finds nothing to do.
+// One round, class 3 (degree above the wavefront class): one workgroup per
+// vertex.  Runs before k_round of the same round; a round handed to the tail
+// has no class-3 vertex, so this kernel then finds nothing to do.
 template <bool FIRST, bool BATCH, typename Off>
-__global__ __launch_bounds__(kBigBlock) void k_big(Args<Off> a, int32_t slot, int32_t collect_stats) {
-  constexpr int BLOCK = kBigBlock;
+__global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot, int32_t collect_stats) {
+  constexpr int BLOCK = kBigBlock, NW = BLOCK / kWave;
   __shared__ int32_t hist[kHistBins];
-  __shared__ int32_t red[kKary * (BLOCK / kWave)];
-  __shared__ unsigned long long red64[kLaneStats * (BLOCK / kWave)];
+  __shared__ int32_t red[kKary * NW];
+  __shared__ unsigned long long red64[kLaneStats * NW];
   Ctl* ctl = a.ctl;
   const int32_t round = ctl->rbase + slot;
   bool dense = false;

@@ -52,6 +52,7 @@ struct ServeArena {
   int32_t* plen = nullptr;
   int32_t* plow = nullptr;
   int32_t* vbase = nullptr;
+  int32_t* slack = nullptr;
   int32_t* gact = nullptr;
   // entry arena
   int32_t* col = nullptr;
@@ -66,7 +67,7 @@ struct ServeArena {
 };
 
 // Bytes of device memory per vertex and per adjacency entry of a resident graph.
-constexpr int64_t kServeVertexBytes = 8 + 4 + 4 + 1 + 8 + 4 + 4 + 4 + 4;
+constexpr int64_t kServeVertexBytes = 8 + 4 + 4 + 1 + 8 + 4 + 4 + 4 + 4 + 4;
 constexpr int64_t kServeEntryBytes = 4 + 4;
 
 kcore_status serve_arena_create(ServeArena* A, int device, int64_t nv, int64_t ne, int32_t max_slots,

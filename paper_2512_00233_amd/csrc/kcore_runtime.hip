@@ -47,6 +47,7 @@ struct Workspace {
   int32_t* plen = nullptr;
   int32_t* plow = nullptr;
   int32_t* vbase = nullptr;
+  int32_t* slack = nullptr;
   int32_t* pruned = nullptr;
   Ctl* ctl = nullptr;
   Ctl* host_ctl = nullptr;      // pinned
@@ -79,12 +80,12 @@ struct Workspace {
   void release() {
     drop_graphs();
     for (void* p : {(void*)stamp, (void*)cls, (void*)lists[0], (void*)lists[1], (void*)slist, (void*)plen,
-                    (void*)plow, (void*)vbase, (void*)pruned})
+                    (void*)plow, (void*)vbase, (void*)slack, (void*)pruned})
       (void)hipFree(p);
     stamp = nullptr;
     cls = nullptr;
     lists[0] = lists[1] = nullptr;
-    slist = plen = plow = vbase = pruned = nullptr;
+    slist = plen = plow = vbase = slack = pruned = nullptr;
     cap_n = 0;
     cap_nnz = 0;
   }
@@ -130,6 +131,7 @@ static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, bool 
             hipMalloc(&ws->slist, sizeof(int32_t) * cap) == hipSuccess &&
             hipMalloc(&ws->plen, sizeof(int32_t) * cap) == hipSuccess &&
             hipMalloc(&ws->plow, sizeof(int32_t) * cap) == hipSuccess &&
+            hipMalloc(&ws->slack, sizeof(int32_t) * cap) == hipSuccess &&
             (!keep_vbase || hipMalloc(&ws->vbase, sizeof(int32_t) * cap) == hipSuccess) &&
             hipMalloc(&ws->pruned, sizeof(int32_t) * cap_e) == hipSuccess;
   if (!ok) {
@@ -241,6 +243,7 @@ static kcore_status launch_chunk(Workspace* ws, const Args<Off>& a, const Tuning
 
 // Timing mode: one round with an event before and after each of its three
 // kernels (compaction, class 3, classes 0..2), then the base advance.
+constexpr int kRoundEvents = 4;
 template <bool BATCH, typename Off>
 static void launch_round_timed(const Args<Off>& a, const Tuning& tu, int cgrid, int32_t collect, hipEvent_t* ev,
                                hipStream_t st) {
@@ -252,6 +255,13 @@ static void launch_round_timed(const Args<Off>& a, const Tuning& tu, int cgrid, 
   hipLaunchKernelGGL((k_round<kBlock, false, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, 0, collect);
   (void)hipEventRecord(ev[3], st);
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a.ctl, 1);
+}
+
+// A kernel's counter, summed over its copies.
+static unsigned long long kstat(const Ctl& h, int kid, int q) {
+  unsigned long long t = 0;
+  for (int c = 0; c < kStatCopies; ++c) t += h.kstats[kid][q][c];
+  return t;
 }
 
 static float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -287,6 +297,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   a.plen = ws->plen;
   a.plow = ws->plow;
   a.ctl = ws->ctl;
+  a.slack = ws->slack;
   a.tail_threshold = tu.tail;
   a.list_cap = tu.list_cap;
   a.one_sided = tu.one_sided;
@@ -300,7 +311,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   double kms[KCORE_K_COUNT] = {0, 0, 0, 0, 0};
   double init_ms = 0;
   if (timing) {
-    kcore_status s = ws->need_events(4 * 64);
+    kcore_status s = ws->need_events(kRoundEvents * 64);
     if (s != KCORE_OK) return s;
   }
   hipEvent_t* ev = timing ? ws->events.data() : nullptr;
@@ -318,17 +329,20 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   unsigned long long prev[KI_COUNT][kLaneStats];
   std::memset(prev, 0, sizeof(prev));
   auto trace_line = [&](const Ctl& h, int32_t r, const char* what, float ms) {
-    unsigned long long d[kLaneStats] = {0, 0, 0, 0, 0, 0};
+    unsigned long long d[2][kLaneStats];  // [0]: class-3 kernels, [1]: classes 0..2
+    std::memset(d, 0, sizeof(d));
     for (int k = 0; k < KI_COUNT; ++k)
       for (int q = 0; q < kLaneStats; ++q) {
-        d[q] += h.kstats[k][q] - prev[k][q];
-        prev[k][q] = h.kstats[k][q];
+        const unsigned long long now = kstat(h, k, q);
+        d[k == KI_BIG_FIRST || k == KI_BIG ? 0 : 1][q] += now - prev[k][q];
+        prev[k][q] = now;
       }
-    std::fprintf(stderr, "[kcore-trace] %s round=%d front=%d/%d/%d/%d dense=%d updates=%llu visits=%llu "
-                 "changes=%llu acts=%llu pw=%llu full=%llu tail=%llu ms=%.3f\n", what, r - r0, h.cnt[r % 3][0],
-                 h.cnt[r % 3][1], h.cnt[r % 3][2], h.cnt[r % 3][3], h.overflow[r % 3][0], d[ST_UPDATES],
-                 d[ST_VISITS], d[ST_CHANGES], d[ST_ACTIVATIONS], d[ST_PRUNE_WRITES], d[ST_FULL_SCANS],
-                 h.stats[ST_TAIL_ROUNDS], ms);
+    std::fprintf(stderr, "[kcore-trace] %s round=%d front=%d/%d/%d/%d dense=%d | big upd=%llu vis=%llu chg=%llu "
+                 "act=%llu full=%llu | small upd=%llu vis=%llu chg=%llu act=%llu full=%llu | tail=%llu ms=%.3f\n",
+                 what, r - r0, h.cnt[r % 3][0], h.cnt[r % 3][1], h.cnt[r % 3][2], h.cnt[r % 3][3],
+                 h.overflow[r % 3][0], d[0][ST_UPDATES], d[0][ST_VISITS], d[0][ST_CHANGES], d[0][ST_ACTIVATIONS],
+                 d[0][ST_FULL_SCANS], d[1][ST_UPDATES], d[1][ST_VISITS], d[1][ST_CHANGES], d[1][ST_ACTIVATIONS],
+                 d[1][ST_FULL_SCANS], h.stats[ST_TAIL_ROUNDS], ms);
   };
   if (timing) {
     KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -348,7 +362,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   int32_t r = r0 + 1;
   for (;;) {
     if (timing) {
-      for (int i = 0; i < K; ++i) launch_round_timed<BATCH, Off>(a, tu, cgrid, collect, ev + 4 * i, st);
+      for (int i = 0; i < K; ++i) launch_round_timed<BATCH, Off>(a, tu, cgrid, collect, ev + kRoundEvents * i, st);
       KC_HIP(hipGetLastError());
     } else {
       kcore_status s = launch_chunk<BATCH, Off>(ws, a, tu, cgrid, K, collect, use_graph, st);
@@ -361,7 +375,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     r = h.rbase;
     if (timing) {
       for (int i = 0; i < K; ++i) {
-        hipEvent_t* e = ev + 4 * i;
+        hipEvent_t* e = ev + kRoundEvents * i;
         kms[KCORE_K_COMPACT] += elapsed(e[0], e[1]);
         kms[KCORE_K_BIG] += elapsed(e[1], e[2]);
         kms[KCORE_K_ROUND] += elapsed(e[2], e[3]);
@@ -383,18 +397,19 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     stats->dense_rounds = (int64_t)hc.stats[ST_DENSE_ROUNDS];
     stats->init_ms = init_ms;
     const int64_t kl[KCORE_K_COUNT] = {1, 1, launches - 1, launches - 1, launches - 1};
+    // counters by public kernel index (the compaction kernel has none)
+    const int kid[KCORE_K_COUNT] = {KI_BIG_FIRST, KI_ROUND_FIRST, KI_BIG, KI_ROUND, -1};
     for (int k = 0; k < KCORE_K_COUNT; ++k) {
       kcore_kernel_stats& o = stats->kernel[k];
       o.launches = kl[k];
       o.ms = kms[k];
-      if (k < KI_COUNT) {
-        const unsigned long long* q = hc.kstats[k];
-        o.vertex_updates = (int64_t)q[ST_UPDATES];
-        o.edge_visits = (int64_t)q[ST_VISITS];
-        o.changes = (int64_t)q[ST_CHANGES];
-        o.activations = (int64_t)q[ST_ACTIVATIONS];
-        o.prune_writes = (int64_t)q[ST_PRUNE_WRITES];
-        o.full_scans = (int64_t)q[ST_FULL_SCANS];
+      if (kid[k] >= 0) {
+        o.vertex_updates = (int64_t)kstat(hc, kid[k], ST_UPDATES);
+        o.edge_visits = (int64_t)kstat(hc, kid[k], ST_VISITS);
+        o.changes = (int64_t)kstat(hc, kid[k], ST_CHANGES);
+        o.activations = (int64_t)kstat(hc, kid[k], ST_ACTIVATIONS);
+        o.prune_writes = (int64_t)kstat(hc, kid[k], ST_PRUNE_WRITES);
+        o.full_scans = (int64_t)kstat(hc, kid[k], ST_FULL_SCANS);
         stats->vertex_updates += o.vertex_updates;
         stats->edge_visits += o.edge_visits;
         stats->changes += o.changes;
@@ -649,6 +664,7 @@ static Args<int64_t> serve_args(const ServeArena* A) {
   a.plen = A->plen;
   a.plow = A->plow;
   a.ctl = static_cast<Ctl*>(A->ctl);
+  a.slack = A->slack;
   a.tail_threshold = A->tu.tail;
   a.list_cap = A->tu.list_cap;
   a.one_sided = A->tu.one_sided;
@@ -661,7 +677,8 @@ void serve_arena_destroy(ServeArena* A) {
   if (A->step_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(A->step_exec));
   A->step_exec = nullptr;
   for (void* p : {(void*)A->row_ptr, (void*)A->est, (void*)A->stamp, (void*)A->cls, (void*)A->lists[0],
-                  (void*)A->lists[1], (void*)A->plen, (void*)A->plow, (void*)A->vbase, (void*)A->gact,
+                  (void*)A->lists[1], (void*)A->plen, (void*)A->plow, (void*)A->vbase, (void*)A->slack, (void*)A->gact,
+
                   (void*)A->col, (void*)A->pruned, A->ctl, A->slots, (void*)A->slot_vb, (void*)A->status})
     if (p) (void)hipFree(p);
   *A = ServeArena();
@@ -687,7 +704,8 @@ kcore_status serve_arena_create(ServeArena* A, int device, int64_t nv, int64_t n
   };
   const bool ok = alloc(&A->row_ptr, nv) && alloc(&A->est, nv) && alloc(&A->stamp, nv) && alloc(&A->cls, nv) &&
                   alloc(&A->lists[0], nv) && alloc(&A->lists[1], nv) && alloc(&A->plen, nv) &&
-                  alloc(&A->plow, nv) && alloc(&A->vbase, nv) && alloc(&A->gact, nv) && alloc(&A->col, A->ne) &&
+                  alloc(&A->plow, nv) && alloc(&A->vbase, nv) && alloc(&A->slack, nv) && alloc(&A->gact, nv) &&
+ alloc(&A->col, A->ne) &&
                   alloc(&A->pruned, A->ne) && alloc(reinterpret_cast<Ctl**>(&A->ctl), 1) &&
                   alloc(reinterpret_cast<SlotDesc**>(&A->slots), max_slots) && alloc(&A->slot_vb, max_slots) &&
                   alloc(&A->status, max_slots);

@@ -35,6 +35,9 @@
     if (e_ != hipSuccess) return kcore::hip_fail(e_, #call); \
   } while (0)
 
+static_assert(kcore::kServeVertexBytes == KCORE_SERVE_VERTEX_BYTES, "vertex footprint out of date");
+static_assert(kcore::kServeEntryBytes == KCORE_SERVE_ENTRY_BYTES, "entry footprint out of date");
+
 namespace kcore {
 namespace {
 

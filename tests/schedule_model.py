@@ -1,0 +1,111 @@
+"""CPU model of the round schedule the GPU kernels follow (test infrastructure).
+
+It replays the rules of the round kernels on small graphs, with the reads,
+writes and atomics of all vertices of a round interleaved at random:
+
+* estimates start at the degree; a frontier vertex recomputes the h-index of
+  the neighbour estimates it read, capped by its own (Sec. II-B, Alg. 1;
+  FastK, Sec. IV, Alg. 4), and writes it in place (other vertices of the same
+  round may read the old or the new value);
+* it records its support slack: neighbours read at or above the new value,
+  minus the value;
+* a change from e to h makes neighbour v (estimate x as read) a candidate when
+  x > h; in the first round every candidate is activated (one-sided rule);
+  later, v is re-activated if it is updated in the same kernel of this round,
+  skipped if it is small and updated after the class-3 kernel, and otherwise
+  charged against its slack when x <= e (the two-sided rule), activated when
+  the slack goes negative;
+* class-3 vertices (degree above `big_deg`) run before the others in a round.
+
+`rule` selects deliberate mistakes, so that tests can show the model would
+notice them: "no_frontier_clause" drops the re-activation of same-kernel
+frontier vertices, "no_kernel_order" runs both classes interleaved while
+keeping the rule that relies on their order.
+"""
+import random
+
+
+def _hindex(vals, cap):
+    vals = sorted(vals, reverse=True)
+    h = 0
+    for i, x in enumerate(vals):
+        if x >= i + 1:
+            h = i + 1
+    return min(h, cap)
+
+
+def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_rounds: int = 10_000):
+    """Coreness of the graph (adjacency lists) under one random schedule; returns (estimates, rounds)."""
+    est = [len(adj[u]) for u in range(n)]
+    big = [len(adj[u]) > big_deg for u in range(n)]
+    stamp = [0] * n
+    slack = [rng.randint(-3, 3) for _ in range(n)]  # meaningless until a vertex's first recomputation
+    r = 1
+    first = True
+    frontier = [u for u in range(n) if est[u] >= 2]
+    rounds = 0
+
+    def proc(u, cur_big):
+        e = est[u]
+        if e < 2:
+            return
+        reads = []
+        for v in adj[u]:
+            reads.append((v, est[v]))
+            yield
+        xs = [x for _, x in reads]
+        h = _hindex(xs, e)
+        if h < e:
+            est[u] = h
+        slack[u] = sum(1 for x in xs if x >= h) - h
+        yield
+        if h == e:
+            return
+        for v, x in reads:
+            if x > h and stamp[v] < r + 1:
+                act = False
+                if first:
+                    act = True
+                elif stamp[v] == r and big[v] == cur_big and rule != "no_frontier_clause":
+                    act = True
+                elif stamp[v] == r and cur_big and not big[v]:
+                    act = False
+                elif x <= e:
+                    old = slack[v]
+                    slack[v] = old - 1
+                    act = old <= 0
+                if act:
+                    stamp[v] = r + 1
+            yield
+
+    while frontier:
+        rounds += 1
+        if rounds > max_rounds:
+            raise RuntimeError("model did not converge")
+        phases = [None] if rule == "no_kernel_order" else [True, False]
+        for ph in phases:
+            gens = [proc(u, big[u]) for u in frontier if ph is None or big[u] == ph]
+            live = list(range(len(gens)))
+            while live:
+                i = rng.choice(live)
+                try:
+                    next(gens[i])
+                except StopIteration:
+                    live.remove(i)
+        first = False
+        r += 1
+        frontier = [u for u in range(n) if stamp[u] == r]
+        rng.shuffle(frontier)
+    return est, rounds
+
+
+def random_graph(rng: random.Random, nmax: int = 28):
+    n = rng.randint(2, nmax)
+    p = rng.uniform(0.05, 0.8)
+    adj = [set() for _ in range(n)]
+    for u in range(n):
+        for v in range(u + 1, n):
+            if rng.random() < p:
+                adj[u].add(v)
+                adj[v].add(u)
+    return n, [sorted(a) for a in adj]

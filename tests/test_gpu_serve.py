@@ -98,7 +98,7 @@ def test_matches_plain_decompose_on_batch_members():
 def test_budget_binds_admission():
     # room for about three of these graphs at a time: the rest wait for space
     graphs = [gg.chung_lu(100_000, 2.5, 12, seed=40 + i) for i in range(10)]
-    fp = max(41 * (g.n + 1) + 8 * g.nnz for g in graphs)
+    fp = max(45 * (g.n + 1) + 8 * g.nnz for g in graphs)
     budget = 3 * fp + (1 << 20)
     with kc().Server(hbm_budget_bytes=budget, entries_per_vertex=12) as s:
         outs = run_all(s, graphs)
@@ -113,7 +113,7 @@ def test_errors_too_large_again_invalid():
     KcoreError = kc().KcoreError
     n = 200_000
     path = gg.from_edges(n, np.arange(n - 1), np.arange(1, n))
-    fp = 41 * (n + 1) + 8 * path.nnz
+    fp = 45 * (n + 1) + 8 * path.nnz
     with kc().Server(hbm_budget_bytes=fp + fp // 2, entries_per_vertex=2, max_queue=2) as s:
         big = gg.erdos_renyi(400_000, 800_000, seed=3)
         with pytest.raises(KcoreError) as ei:

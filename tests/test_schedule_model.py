@@ -1,0 +1,44 @@
+"""The activation rules of the round kernels, checked on the host: under many
+random interleavings of reads, writes and atomics the schedule model reaches
+the oracle's coreness, and each deliberate mistake in the rules is caught."""
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.schedule_model import random_graph, run_model
+
+
+def graphs(count, seed):
+    rng = random.Random(seed)
+    out = []
+    for _ in range(count):
+        n, adj = random_graph(rng)
+        rp = np.zeros(n + 1, np.int64)
+        for u in range(n):
+            rp[u + 1] = rp[u] + len(adj[u])
+        ci = np.array([v for a in adj for v in a], np.int32)
+        out.append((n, adj, oracle.coreness(rp, ci).tolist()))
+    return out
+
+
+CASES = graphs(1500, seed=11)
+
+
+def test_model_reaches_the_coreness_under_random_schedules():
+    rng = random.Random(5)
+    for n, adj, ref in CASES:
+        for big_deg in (rng.randint(1, 8), 1 << 30):
+            got, _ = run_model(n, adj, rng, big_deg)
+            assert got == ref, (n, adj, big_deg)
+
+
+@pytest.mark.parametrize("rule", ["no_frontier_clause", "no_kernel_order"])
+def test_model_catches_broken_rules(rule):
+    rng = random.Random(7)
+    wrong = 0
+    for n, adj, ref in CASES:
+        got, _ = run_model(n, adj, rng, rng.randint(1, 8), rule=rule)
+        wrong += got != ref
+    assert wrong > 0
