@@ -322,6 +322,10 @@ def main():
     ap.add_argument("--autotune", default="", help="batch workload: run the autotuner and save to this JSON")
     ap.add_argument("--also", default="road,er_small", help="other plain workloads to report (comma list)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--roofline-runs", type=int, default=ROOFLINE_RUNS,
+                    help="instrumented decompositions (per-kernel HIP events and counters)")
+    ap.add_argument("--pmc-calibrate", type=int, default=0, metavar="BYTES",
+                    help="copy a device buffer of BYTES once first (reference for rocprofv3 byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -339,6 +343,13 @@ def main():
         print(json.dumps({"error": "no GPU available"}))
         sys.exit(1)
     kc.load()
+    if args.pmc_calibrate:
+        src = torch.ones(args.pmc_calibrate // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "batch":
         print(json.dumps(run_batch_workload(args, torch, kc, gg, np)), flush=True)
         return
@@ -346,14 +357,14 @@ def main():
         print(json.dumps(run_serve_workload(args, torch, kc, gg, np)), flush=True)
         return
 
-    g, core, st, ms, wall, per_kernel = run_workload(args.workload, args.steps, args.warmup, torch, kc, gg,
-                                                     ROOFLINE_RUNS)
+    runs = max(1, args.roofline_runs)
+    g, core, st, ms, wall, per_kernel = run_workload(args.workload, args.steps, args.warmup, torch, kc, gg, runs)
     m_und = g.nnz // 2
     gteps = m_und / (ms * 1e-3) / 1e9
-    roofline = roofline_of(per_kernel, args.workload, kc)
-    kernels = {kc.KERNEL_SYMBOLS[k]: {"ms_per_run": round(v["ms"] / ROOFLINE_RUNS, 4),
-                                      "launches_per_run": v["launches"] // ROOFLINE_RUNS,
-                                      "algorithmic_gb_per_run": round(v["bytes"] / ROOFLINE_RUNS / 1e9, 4)}
+    roofline = roofline_of(per_kernel, args.workload, kc, runs)
+    kernels = {kc.KERNEL_SYMBOLS[k]: {"ms_per_run": round(v["ms"] / runs, 4),
+                                      "launches_per_run": v["launches"] // runs,
+                                      "algorithmic_gb_per_run": round(v["bytes"] / runs / 1e9, 4)}
                for k, v in per_kernel.items()}
 
     result = {

@@ -96,9 +96,10 @@ __device__ __forceinline__ Sink make_sink(const Args<Off>& a, int32_t next_round
 // round (dense) and in one-sided mode every candidate with x > h is activated.
 // Winners of the round-stamp dedup (atomicMax) are appended to the list of
 // their degree class with one atomic per class per wavefront, unless the next
-// round already rebuilds its lists by compaction.  Loads and atomics of a lane
-// are issued together at each step.  Every active lane of the wavefront must
-// call this.
+// round already rebuilds its lists by compaction (then, in the first round,
+// the stamps are plain stores and the activation count includes repeats).
+// Loads and atomics of a lane are issued together at each step.  Every active
+// lane of the wavefront must call this.
 template <int N, bool BIG, typename Off>
 __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink& s, int32_t (&v)[N],
                                                  const int32_t (&x)[N], const bool (&in)[N], int32_t e, int32_t h,
@@ -111,10 +112,24 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
     any |= cand[i];
   }
   if (!ballot(any)) return;
+  const bool always = a.one_sided || dense;
+  const bool compact_next = s.overflow && *(volatile int32_t*)s.overflow;
+  if (always && compact_next) {
+    // every candidate is activated and the next round's lists come from the
+    // stamps: plain stores (all writers of this round store the same value)
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (cand[i]) a.stamp[v[i]] = s.stamp;
+    uint32_t nc = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) nc += cand[i];
+    st.v[ST_ACTIVATIONS] += nc;
+    if (a.gact && nc) a.gact[gb] = s.stamp;
+    return;
+  }
   int32_t sv[N], cv[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) sv[i] = cand[i] ? a.stamp[v[i]] : INT32_MAX;
-  const bool always = a.one_sided || dense;
   // the class is needed for frontier members (which kernel updates them) and for winners
 #pragma unroll
   for (int i = 0; i < N; ++i) cv[i] = (!always && cand[i] && sv[i] == round) ? (int32_t)a.cls[v[i]] : -1;
@@ -143,7 +158,6 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
   st.v[ST_ACTIVATIONS] += __popc(first);
   // served graphs: the graph has work in the next round (all candidates share the current vertex's graph)
   if (a.gact && first) a.gact[gb] = s.stamp;
-  const bool compact_next = s.overflow && *(volatile int32_t*)s.overflow;
   if (compact_next || !ballot(first != 0)) return;
 #pragma unroll
   for (int i = 0; i < N; ++i)
@@ -310,6 +324,10 @@ __device__ __forceinline__ void upd_lane(const Args<Off>& a, const Sink& s, int3
   activate_changed<kLaneMaxDeg, false>(a, s, c, x, in, e, h, dense, round, st, gb);
 }
 
+// Threshold of a pruned list built after a full scan that gave h: neighbours
+// whose estimate is at least this are kept.
+__device__ __forceinline__ int32_t prune_low(int32_t h) { return max(2, h - (h * kPruneMarginNum) / kPruneMarginDen); }
+
 // ------------------------------------------------------------------ class 1: 16-lane group per vertex
 template <bool BATCH, typename Off>
 __device__ __forceinline__ void upd_group(const Args<Off>& a, const Sink& s, int32_t u, bool valid, bool dense,
@@ -396,7 +414,7 @@ __device__ __forceinline__ void upd_wave(const Args<Off>& a, const Sink& s, int3
     }
     h = kary_regs<kWave, R>(x, e, 1, true, cnt);
     if (a.prune) {
-      const int32_t L2 = max(2, (3 * h) / 4);
+      const int32_t L2 = prune_low(h);
       int32_t off = 0;
 #pragma unroll
       for (int i = 0; i < R; ++i) {
@@ -750,7 +768,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
       inreg = true;
       h = kary_block<BLOCK, R>(x, e, 1, red, cnt);
       if (a.prune) {
-        const int32_t L2 = max(2, (3 * h) / 4);
+        const int32_t L2 = prune_low(h);
         int32_t mine = 0;
 #pragma unroll
         for (int i = 0; i < R; ++i) mine += (tid + BLOCK * i < len) && x[i] >= L2;
@@ -791,7 +809,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
   // streaming pass over the list, U entries per thread at a time: activation
   // and/or rebuilding the pruned list (one workgroup scan per U * BLOCK entries)
   constexpr int U = 8;
-  const int32_t L2 = max(2, (3 * h) / 4);
+  const int32_t L2 = prune_low(h);
   int32_t written = 0;
   for (int32_t j0 = 0; j0 < len; j0 += BLOCK * U) {
     int32_t v[U], xv[U];
