@@ -60,6 +60,11 @@ def measured_traffic(workload, kernel):
     return k.get("bytes_per_launch_scaled")
 
 
+def progress(msg):
+    """Progress line on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_bytes(k, off_bytes=8):
     return algorithmic_bytes(k.vertex_updates, k.edge_visits, k.changes, k.activations, off_bytes)
 
@@ -117,8 +122,10 @@ def run_batch_workload(args, torch, kc, gg, np):
     """Batched form: G graphs in one launch sequence vs one plain call per graph."""
     import oracle
     t0 = time.perf_counter()
+    progress(f"generating {args.graphs} graphs")
     b = gg.batch(args.graphs, seed=4, nmin=1000, nmax=1_000_000)
     gen_s = time.perf_counter() - t0
+    progress(f"generated in {gen_s:.1f} s: N={int(b.graph_vtx_off[-1])} entries={b.col_idx.size}")
     G, N, NNZ = b.num_graphs, int(b.graph_vtx_off[-1]), int(b.col_idx.size)
     dev = torch.device("cuda:0")
     vo = torch.from_numpy(b.graph_vtx_off).to(dev)
@@ -138,6 +145,7 @@ def run_batch_workload(args, torch, kc, gg, np):
         from paper_2512_00233_amd import autotune
         tuned = autotune.tune_and_save(vo, rp, ci, args.autotune, reps=1, out=out)
     st = kc.Stats()
+    progress("batched runs")
     kc.decompose_batch(vo, rp, ci, out=out, stats=st, tuning=kc.Tuning(timing=1))
     for _ in range(args.warmup):
         kc.decompose_batch(vo, rp, ci, out=out)
@@ -151,6 +159,7 @@ def run_batch_workload(args, torch, kc, gg, np):
     ms_batch = e0.elapsed_time(e1) / args.steps
     core_batch = out.cpu().numpy()
     # plain: one kcore_decompose per graph, back to back on the same stream
+    progress("plain runs, one call per graph")
     out.fill_(-1)
     for rpg, cig, og in plain[: min(G, 8)]:
         kc.decompose(rpg, cig, out=og)
@@ -181,6 +190,7 @@ def run_batch_workload(args, torch, kc, gg, np):
         res["autotuned"] = tuned
     if not args.no_cpu_baseline:
         threads = os.cpu_count() or 1
+        progress(f"oracle on {threads} threads")
         t = time.perf_counter()
         ref = oracle.coreness_batch(b.graph_vtx_off, b.row_ptr, b.col_idx, threads=threads)
         dt = time.perf_counter() - t
@@ -198,6 +208,7 @@ def run_serve_workload(args, torch, kc, gg, np):
     import oracle
     rng = np.random.default_rng(5)
     t0 = time.perf_counter()
+    progress(f"generating a pool of {args.pool} graphs")
     pool_b = gg.batch(args.pool, seed=6, nmin=1000, nmax=4_000_000)
     pool = [pool_b.graph(i) for i in range(pool_b.num_graphs)]
     gen_s = time.perf_counter() - t0
@@ -248,14 +259,17 @@ def run_serve_workload(args, torch, kc, gg, np):
         o = torch.empty(pool[g].n, dtype=torch.int32, pin_memory=True)
         wsrv.wait(wsrv.submit(pinned[g][0], pinned[g][1], o), timeout_s=120)
     wsrv.close()
+    progress(f"saturating burst of {N} requests")
     burst_wall, burst = serve_run(np.zeros(N))
     capacity = burst["graphs_per_s"]
     lam = args.load * capacity
     arrivals = np.cumsum(rng.exponential(1.0 / lam, N))
     arrivals -= arrivals[0]
+    progress(f"Poisson arrivals at {lam:.1f}/s")
     pois_wall, pois = serve_run(arrivals)
 
     # FIFO baseline: the same Poisson trace served by one plain call at a time
+    progress("FIFO plain calls on the same trace")
     dev = torch.device("cuda:0")
     lat = []
     start = time.perf_counter()

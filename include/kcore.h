@@ -64,7 +64,11 @@ typedef struct kcore_tuning {
                               its lists from the round stamps (0: library default 8192) */
   int32_t no_prune;        /* 1: disable the pruned adjacency (always scan the full neighbour list) */
   int32_t no_graph;        /* 1: launch every round directly instead of replaying captured hipGraphs */
-  int32_t reserved[4];
+  int32_t max_rounds;      /* > 0: stop after this many rounds (the first round counts as round 1; the
+                              single-workgroup tail is off) and leave the estimates reached so far in
+                              out_core: an upper bound of the coreness, equal to it once the run has
+                              converged.  Instrumentation of the convergence; 0: run to the fixpoint */
+  int32_t reserved[3];
 } kcore_tuning;
 
 /* Round kernels, as indices into kcore_stats.kernel.  The first round (every
@@ -139,6 +143,29 @@ kcore_status kcore_decompose32(int64_t n, const int32_t* row_ptr, const int32_t*
 /* kcore_decompose with explicit tuning (NULL = defaults) and optional statistics (NULL = none). */
 kcore_status kcore_decompose_ex(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
                                 const kcore_tuning* tuning, kcore_stats* stats, void* stream);
+
+/* One round of a run recorded by kcore_decompose_rounds. */
+typedef struct kcore_round_record {
+  int32_t round;           /* 1 = the first round (every vertex of degree >= 2) */
+  int32_t tail_rounds;     /* rounds run inside this launch by the single-workgroup tail (0: none) */
+  int64_t vertex_updates;  /* vertices whose h-index was recomputed in this round (with a tail: its rounds) */
+  int64_t edge_visits;     /* adjacency entries read by those recomputations */
+  int64_t changes;         /* estimate decreases */
+  int64_t activations;     /* vertices put in the next frontier */
+  double ms;               /* duration of the round's kernels (HIP events on the stream) */
+} kcore_round_record;
+
+/*
+ * kcore_decompose_ex launching one round at a time (instrumentation of the
+ * convergence, as in the paper's per-iteration figures): each round is
+ * bracketed by HIP events and its work counters are read back, one
+ * kcore_round_record per round into records[0 .. max_records) (host memory;
+ * later rounds are not recorded); *n_records receives the number written.
+ * Slower than kcore_decompose; the result is the same.
+ */
+kcore_status kcore_decompose_rounds(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
+                                    const kcore_tuning* tuning, kcore_round_record* records, int32_t max_records,
+                                    int32_t* n_records, void* stream);
 
 /*
  * kcore_decompose_batch -- coreness of many independent graphs in one launch

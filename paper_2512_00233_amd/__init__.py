@@ -15,7 +15,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["decompose", "decompose_batch", "autotune_batch", "tuning_cache_set", "tuning_cache_get", "Tuning",
+__all__ = ["decompose", "decompose_rounds", "decompose_batch", "autotune_batch", "tuning_cache_set", "tuning_cache_get", "Tuning",
            "Stats", "KcoreError", "Server", "ServeConfig", "Completion", "library_path", "load", "version"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -49,7 +49,8 @@ class Tuning(ctypes.Structure):
         ("list_cap", ctypes.c_int32),
         ("no_prune", ctypes.c_int32),
         ("no_graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("max_rounds", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -103,6 +104,22 @@ class Stats(ctypes.Structure):
         d = {name: getattr(self, name) for name, _ in self._fields_ if name != "kernel"}
         d["kernels"] = {k: self.kernel[i].as_dict() for i, k in enumerate(KERNELS)}
         return d
+
+
+class RoundRecord(ctypes.Structure):
+    """Mirror of ``kcore_round_record``."""
+    _fields_ = [
+        ("round", ctypes.c_int32),
+        ("tail_rounds", ctypes.c_int32),
+        ("vertex_updates", ctypes.c_int64),
+        ("edge_visits", ctypes.c_int64),
+        ("changes", ctypes.c_int64),
+        ("activations", ctypes.c_int64),
+        ("ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class ServeConfig(ctypes.Structure):
@@ -174,6 +191,9 @@ def load():
     lib.kcore_decompose32.argtypes = [i64, vp, vp, vp, vp]
     lib.kcore_decompose_ex.restype = i32
     lib.kcore_decompose_ex.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats), vp]
+    lib.kcore_decompose_rounds.restype = i32
+    lib.kcore_decompose_rounds.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(RoundRecord), i32,
+                                           ctypes.POINTER(i32), vp]
     lib.kcore_decompose_batch.restype = i32
     lib.kcore_decompose_batch.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats), vp]
     lib.kcore_autotune_batch.restype = i32
@@ -259,6 +279,25 @@ def decompose(row_ptr, col_idx, out=None, tuning: Tuning | None = None, stats: S
                                       ctypes.byref(tuning) if tuning is not None else None,
                                       ctypes.byref(stats) if stats is not None else None, st))
     return out
+
+
+def decompose_rounds(row_ptr, col_idx, out=None, tuning: Tuning | None = None, max_records: int = 1 << 16,
+                     stream=None):
+    """``decompose`` launching one round at a time; returns (out, list of per-round records)."""
+    import torch
+    lib = load()
+    if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32 or not (row_ptr.is_cuda and col_idx.is_cuda):
+        raise TypeError("row_ptr must be an int64 and col_idx an int32 CUDA tensor")
+    n = row_ptr.numel() - 1
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+    recs = (RoundRecord * max_records)()
+    got = ctypes.c_int32()
+    col_ptr = col_idx.data_ptr() if col_idx.numel() else out.data_ptr()
+    _check(lib.kcore_decompose_rounds(n, row_ptr.data_ptr(), col_ptr, out.data_ptr(),
+                                      ctypes.byref(tuning) if tuning is not None else None, recs, max_records,
+                                      ctypes.byref(got), _stream_handle(stream)))
+    return out, [recs[i].as_dict() for i in range(got.value)]
 
 
 def _check_batch(graph_vtx_off, row_ptr, col_idx):

@@ -26,6 +26,7 @@ struct Tuning {
   int list_cap;   // sparse list capacity per class
   int prune;      // pruned adjacency on/off
   int use_graph;  // capture chunks of round launches as hipGraphs
+  int max_rounds; // > 0: stop after this many rounds (tail off)
 };
 
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus);

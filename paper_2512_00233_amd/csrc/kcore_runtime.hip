@@ -162,6 +162,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.list_cap = 8192;
   r.prune = 1;
   r.use_graph = 1;
+  r.max_rounds = 0;
   if (const char* e = std::getenv("KCORE_TAIL")) r.tail = std::atoi(e);
   if (t) {
     if (t->thread_max_deg > 0) r.t0 = std::min(t->thread_max_deg, kLaneMaxDeg);
@@ -177,6 +178,10 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
     if (t->list_cap > 0) r.list_cap = t->list_cap;
     r.prune = t->no_prune != 1;
     r.use_graph = t->no_graph != 1;
+    if (t->max_rounds > 0) {
+      r.max_rounds = t->max_rounds;
+      r.tail = 0;
+    }
   }
   r.t0 = std::max(r.t0, 1);
   r.t1 = std::max(r.t1, r.t0);
@@ -274,7 +279,8 @@ static float elapsed(hipEvent_t a, hipEvent_t b) {
 // row_ptr holds global edge offsets; with BATCH, col holds graph-local ids.
 template <bool BATCH, typename Off>
 static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off* row_ptr, const int32_t* col,
-                               int32_t* out, const Tuning& tu, kcore_stats* stats, hipStream_t st) {
+                               int32_t* out, const Tuning& tu, kcore_stats* stats, hipStream_t st,
+                               std::vector<kcore_round_record>* rec = nullptr) {
   const int init_grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
   const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, (int64_t)ws->num_cus * 8));
   if (ws->epoch > (1 << 29)) {
@@ -303,8 +309,9 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   a.one_sided = tu.one_sided;
   a.prune = tu.prune;
   a.gact = nullptr;
-  const int32_t collect = stats ? 1 : 0;
-  const bool trace = env_flag("KCORE_TRACE");
+  const int32_t collect = (stats || rec) ? 1 : 0;
+  const bool trace_env = env_flag("KCORE_TRACE");
+  const bool trace = trace_env || rec != nullptr;  // one round per launch, counters read after each
   const bool timing = tu.timing || trace;
   const bool use_graph = tu.use_graph && !timing && st != nullptr;  // no capture on the null stream
   const int32_t r0 = ws->epoch;
@@ -328,6 +335,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   KC_HIP(hipGetLastError());
   unsigned long long prev[KI_COUNT][kLaneStats];
   std::memset(prev, 0, sizeof(prev));
+  unsigned long long prev_tail = 0;
   auto trace_line = [&](const Ctl& h, int32_t r, const char* what, float ms) {
     unsigned long long d[2][kLaneStats];  // [0]: class-3 kernels, [1]: classes 0..2
     std::memset(d, 0, sizeof(d));
@@ -337,6 +345,20 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
         d[k == KI_BIG_FIRST || k == KI_BIG ? 0 : 1][q] += now - prev[k][q];
         prev[k][q] = now;
       }
+    if (rec) {
+      kcore_round_record x;
+      std::memset(&x, 0, sizeof(x));
+      x.round = (int32_t)rec->size() + 1;
+      x.tail_rounds = (int32_t)(h.stats[ST_TAIL_ROUNDS] - prev_tail);
+      x.vertex_updates = (int64_t)(d[0][ST_UPDATES] + d[1][ST_UPDATES]);
+      x.edge_visits = (int64_t)(d[0][ST_VISITS] + d[1][ST_VISITS]);
+      x.changes = (int64_t)(d[0][ST_CHANGES] + d[1][ST_CHANGES]);
+      x.activations = (int64_t)(d[0][ST_ACTIVATIONS] + d[1][ST_ACTIVATIONS]);
+      x.ms = ms;
+      rec->push_back(x);
+    }
+    prev_tail = h.stats[ST_TAIL_ROUNDS];
+    if (!trace_env) return;
     std::fprintf(stderr, "[kcore-trace] %s round=%d front=%d/%d/%d/%d dense=%d | big upd=%llu vis=%llu chg=%llu "
                  "act=%llu full=%llu | small upd=%llu vis=%llu chg=%llu act=%llu full=%llu | tail=%llu ms=%.3f\n",
                  what, r - r0, h.cnt[r % 3][0], h.cnt[r % 3][1], h.cnt[r % 3][2], h.cnt[r % 3][3],
@@ -350,17 +372,25 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     init_ms = elapsed(ev[0], ev[1]);
     kms[KCORE_K_BIG_FIRST] = elapsed(ev[1], ev[2]);
     kms[KCORE_K_ROUND_FIRST] = elapsed(ev[2], ev[3]);
-    if (trace) {
+    if (trace_env)
       std::fprintf(stderr, "[kcore-trace] n=%lld nnz=%lld pop=%d/%d/%d/%d init_ms=%.3f\n", (long long)n,
                    (long long)nnz, ws->host_ctl->pop[0], ws->host_ctl->pop[1], ws->host_ctl->pop[2],
                    ws->host_ctl->pop[3], init_ms);
-      trace_line(*ws->host_ctl, r0 + 1, "first", (float)(kms[0] + kms[1]));
-    }
+    if (trace) trace_line(*ws->host_ctl, r0 + 1, "first", (float)(kms[0] + kms[1]));
   }
   int64_t launches = 1;
   int K = trace ? 1 : tu.poll;
   int32_t r = r0 + 1;
   for (;;) {
+    if (tu.max_rounds > 0) {
+      if (launches >= tu.max_rounds) {
+        KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        KC_HIP(hipStreamSynchronize(st));
+        r = ws->host_ctl->rbase;
+        break;
+      }
+      K = (int)std::min<int64_t>(K, tu.max_rounds - launches);
+    }
     if (timing) {
       for (int i = 0; i < K; ++i) launch_round_timed<BATCH, Off>(a, tu, cgrid, collect, ev + kRoundEvents * i, st);
       KC_HIP(hipGetLastError());
@@ -444,7 +474,8 @@ static kcore_status validate_csr(Workspace* ws, int64_t n, const Off* row_ptr, c
 
 template <typename Off>
 static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t* col, int32_t* out,
-                                   const kcore_tuning* tuning, kcore_stats* stats, hipStream_t st) {
+                                   const kcore_tuning* tuning, kcore_stats* stats, hipStream_t st,
+                                   std::vector<kcore_round_record>* rec = nullptr) {
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (n < 0 || n > INT32_MAX) return fail(KCORE_E_INVALID, "n must be in [0, 2^31-1]");
   if (n == 0) return KCORE_OK;
@@ -465,7 +496,7 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
     if (s != KCORE_OK) return s;
   }
   const Tuning tu = resolve_tuning(tuning, ws->num_cus);
-  return run_rounds<false, Off>(ws, n, nnz, row_ptr, col, out, tu, stats, st);
+  return run_rounds<false, Off>(ws, n, nnz, row_ptr, col, out, tu, stats, st, rec);
 }
 
 template <typename Off>
@@ -812,6 +843,21 @@ kcore_status kcore_decompose32(int64_t n, const int32_t* row_ptr, const int32_t*
 kcore_status kcore_decompose_ex(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
                                 const kcore_tuning* tuning, kcore_stats* stats, void* stream) {
   return decompose_impl<int64_t>(n, row_ptr, col_idx, out_core, tuning, stats, (hipStream_t)stream);
+}
+
+kcore_status kcore_decompose_rounds(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
+                                    const kcore_tuning* tuning, kcore_round_record* records, int32_t max_records,
+                                    int32_t* n_records, void* stream) {
+  if (!n_records || max_records < 0 || (max_records > 0 && !records))
+    return fail(KCORE_E_INVALID, "bad record buffer arguments");
+  *n_records = 0;
+  std::vector<kcore_round_record> rec;
+  const kcore_status s =
+      decompose_impl<int64_t>(n, row_ptr, col_idx, out_core, tuning, nullptr, (hipStream_t)stream, &rec);
+  const int32_t k = (int32_t)std::min<size_t>(rec.size(), (size_t)max_records);
+  if (k > 0) std::memcpy(records, rec.data(), sizeof(kcore_round_record) * k);
+  *n_records = k;
+  return s;
 }
 
 kcore_status kcore_decompose_batch(int32_t num_graphs, const int64_t* graph_vtx_off, const int64_t* row_ptr,

@@ -214,3 +214,38 @@ def test_validation_mode_rejects_bad_csr(monkeypatch):
     oob_ci = np.array([1, 7], np.int32)
     with pytest.raises(kc_.KcoreError, match="range"):
         run_gpu(np.array([0, 1, 2], np.int64), oob_ci)
+
+
+# ---------------------------------------------------------------- convergence instrumentation
+def test_runs_stopped_early_give_upper_bounds():
+    # estimates only decrease and never drop below the coreness (Sec. III; Montresor et al.)
+    kc_ = kc()
+    g = gg.workload("rmat16")
+    ref = oracle.coreness(g.row_ptr, g.col_idx)
+    deg = np.diff(g.row_ptr)
+    for r in (1, 2, 3, 5, 8):
+        st = kc_.Stats()
+        est = run_gpu(g.row_ptr, g.col_idx, tuning=kc_.Tuning(max_rounds=r), stats=st)
+        assert (est >= ref).all() and (est <= deg).all(), r
+        assert st.rounds <= r and st.tail_rounds == 0
+    assert np.array_equal(run_gpu(g.row_ptr, g.col_idx, tuning=kc_.Tuning(max_rounds=1 << 20)), ref)
+
+
+def test_convergence_profile_reaches_the_coreness():
+    from paper_2512_00233_amd import convergence
+    g = gg.workload("road_512")
+    dev = torch.device("cuda:0")
+    rows, total = convergence.profile(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev))
+    assert len(rows) == total and total >= 2
+    assert rows[0]["active"] > 0 and rows[-1]["exact_share"] == 1.0
+
+
+def test_round_by_round_records():
+    kc_ = kc()
+    g = gg.workload("rmat16")
+    dev = torch.device("cuda:0")
+    out, recs = kc_.decompose_rounds(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev))
+    assert np.array_equal(out.cpu().numpy(), oracle.coreness(g.row_ptr, g.col_idx))
+    assert len(recs) >= 2 and [r["round"] for r in recs] == list(range(1, len(recs) + 1))
+    assert recs[0]["vertex_updates"] == int((np.diff(g.row_ptr) >= 2).sum())  # the first round: degree >= 2
+    assert all(r["vertex_updates"] > 0 and r["ms"] > 0 for r in recs)
