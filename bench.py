@@ -36,9 +36,13 @@ def algorithmic_bytes(updates, visits, changes, acts, off_bytes=8):
     return (2 * off_bytes + 8) * updates + 8 * visits + 4 * changes + 9 * acts
 
 
+KERNEL_SOURCES = ("kcore_kernels.h", "kcore_kernels_impl.h")
+
+
 def kernel_source_hash():
+    """Hash of the device code; counter summaries taken on other device code are not used."""
     h = hashlib.sha1()
-    for fn in sorted(os.listdir(os.path.join(ROOT, "paper_2512_00233_amd", "csrc"))):
+    for fn in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2512_00233_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:12]
@@ -111,11 +115,18 @@ def roofline_of(per_kernel, workload, kc, runs=ROOFLINE_RUNS):
     launches = max(k["launches"], 1)
     achieved = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
     symbol = kc.KERNEL_SYMBOLS[name]
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, symbol),
-            "kernel": symbol, "launches_per_run": round(launches / max(1, runs)),
-            "bytes_per_launch": int(k["bytes"] / launches), "avg_launch_us": round(k["ms"] / launches * 1e3, 3),
-            "share_of_kernel_time": round(k["ms"] / max(1e-9, sum(v["ms"] for v in per_kernel.values())), 3)}
+    traffic = measured_traffic(workload, symbol)
+    avg_s = k["ms"] / launches * 1e-3
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "kernel": symbol, "launches_per_run": round(launches / max(1, runs)),
+           "bytes_per_launch": int(k["bytes"] / launches), "avg_launch_us": round(avg_s * 1e6, 3),
+           "share_of_kernel_time": round(k["ms"] / max(1e-9, sum(v["ms"] for v in per_kernel.values())), 3)}
+    if traffic and avg_s > 0:
+        # counter bytes (L2 <-> memory fabric, scaled) over the same average launch duration
+        out["traffic_gbs"] = round(traffic / avg_s / 1e9, 1)
+        out["traffic_frac"] = round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+    return out
 
 
 def run_batch_workload(args, torch, kc, gg, np):

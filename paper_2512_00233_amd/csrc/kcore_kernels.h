@@ -63,6 +63,8 @@ constexpr int kBigBlock = 256;      // class 3: one workgroup per vertex
 constexpr int kBigRegs = 8;         // values per thread held in registers (2048 per workgroup)
 constexpr int kKary = 8;            // thresholds per pass of the k-ary search
 constexpr int kHistBins = 4096;     // LDS histogram bins of the one-pass search (16 KB)
+// Order of the two update kernels in a round: class 3 first (true) or classes 0..2 first.
+constexpr bool kBigFirst = true;
 constexpr int kPruneMarginNum = 1;  // pruned lists keep estimates >= h - h * num / den
 constexpr int kPruneMarginDen = 4;
 

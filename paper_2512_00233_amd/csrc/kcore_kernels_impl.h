@@ -83,15 +83,16 @@ __device__ __forceinline__ Sink make_sink(const Args<Off>& a, int32_t next_round
 // was last recomputed): the loss is subtracted, and v is activated only when
 // the slack goes negative.
 // A vertex of the current frontier is updated in this round too.  Class-3
-// vertices are updated by the class-3 kernel, which completes before the
-// classes-0..2 kernel of the same round starts (in the tail: before the small
-// classes, behind a barrier).  So, with BIG telling which kernel the current
-// vertex belongs to:
+// vertices are updated by the class-3 kernel, the others by the classes-0..2
+// kernel; one of the two completes before the other starts (kBigFirst; in the
+// tail the same order holds behind a barrier).  So, with BIG telling which
+// kernel the current vertex belongs to:
 //  * v updated by the same kernel may have read the old value of the current
 //    vertex, and x may be stale: v is re-activated;
-//  * v small, current vertex class 3: v is updated later and reads the new value;
-//  * v class 3, current vertex small: v's update is done, x is its new value and
-//    its slack counts the current vertex's old value: the exact rule applies.
+//  * v updated by the later kernel (the current one runs first): v reads the
+//    new value, nothing to do;
+//  * v updated by the earlier kernel: v's update is done, x is its new value
+//    and its slack counts the current vertex's old value: the exact rule applies.
 // A vertex already activated for the next round needs nothing.  In the first
 // round (dense) and in one-sided mode every candidate with x > h is activated.
 // Winners of the round-stamp dedup (atomicMax) are appended to the list of
@@ -140,7 +141,7 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
     bool w = false, d = false;
     if (always) w = true;
     else if (sv[i] == round && (cv[i] == 3) == BIG) w = true;
-    else if (sv[i] == round && BIG) w = false;
+    else if (sv[i] == round && BIG == kBigFirst) w = false;  // v's kernel runs after this one
     else if (x[i] <= e) d = true;
     want |= (w ? 1u : 0u) << i;
     sub |= (d ? 1u : 0u) << i;
@@ -996,9 +997,17 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
       break;
     }
     const Sink s = make_sink(a, r + 1, ctl->tail_cnt[(t + 1) & 1], nullptr, false);
-    for (int32_t i = 0; i < f.n[3]; ++i) upd_big_lite<BLOCK, BATCH>(a, s, f.list[f.b[3] + i], r, st, red);
-    __syncthreads();  // class-3 updates of this round are visible before the small classes run
-    sweep_small<BLOCK, BATCH>(a, s, f, false, r, 0, 1, st);
+    // the two groups of classes in the order of the round kernels; the barrier
+    // makes the first group's updates visible to the second
+    if (kBigFirst)
+      for (int32_t i = 0; i < f.n[3]; ++i) upd_big_lite<BLOCK, BATCH>(a, s, f.list[f.b[3] + i], r, st, red);
+    else
+      sweep_small<BLOCK, BATCH>(a, s, f, false, r, 0, 1, st);
+    __syncthreads();
+    if (kBigFirst)
+      sweep_small<BLOCK, BATCH>(a, s, f, false, r, 0, 1, st);
+    else
+      for (int32_t i = 0; i < f.n[3]; ++i) upd_big_lite<BLOCK, BATCH>(a, s, f.list[f.b[3] + i], r, st, red);
     __syncthreads();
     if (t > 0 && tid < kClasses) ctl->tail_cnt[t & 1][tid] = 0;  // reused by round t+2
     __syncthreads();

@@ -199,6 +199,25 @@ static bool env_flag(const char* name) {
 // ------------------------------------------------------------------ driver
 constexpr int kBlock = 256;
 
+// The two update kernels of a round (slot relative to the round base), in
+// kBigFirst order.  With ev (3 events) the launches are bracketed: ev[0]
+// before the first, ev[1] between, ev[2] after the second.
+template <bool FIRST, bool BATCH, typename Off>
+static void launch_updates(const Args<Off>& a, const Tuning& tu, int32_t slot, int32_t collect, hipStream_t st,
+                           hipEvent_t* ev) {
+  if (ev) (void)hipEventRecord(ev[0], st);
+  if (kBigFirst)
+    hipLaunchKernelGGL((k_big<FIRST, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, slot, collect);
+  else
+    hipLaunchKernelGGL((k_round<kBlock, FIRST, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, slot, collect);
+  if (ev) (void)hipEventRecord(ev[1], st);
+  if (kBigFirst)
+    hipLaunchKernelGGL((k_round<kBlock, FIRST, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, slot, collect);
+  else
+    hipLaunchKernelGGL((k_big<FIRST, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, slot, collect);
+  if (ev) (void)hipEventRecord(ev[2], st);
+}
+
 // Launch one chunk of K rounds (slots 0..K-1 relative to ctl->rbase) and
 // advance the round base.  With use_graph the chunk is captured once per
 // launch shape and replayed.
@@ -208,8 +227,7 @@ static kcore_status launch_chunk(Workspace* ws, const Args<Off>& a, const Tuning
   auto enqueue = [&]() {
     for (int i = 0; i < K; ++i) {
       hipLaunchKernelGGL((k_compact<false, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, i);
-      hipLaunchKernelGGL((k_big<false, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, i, collect);
-      hipLaunchKernelGGL((k_round<kBlock, false, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, i, collect);
+      launch_updates<false, BATCH, Off>(a, tu, i, collect, st, nullptr);
     }
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a.ctl, K);
   };
@@ -254,11 +272,7 @@ static void launch_round_timed(const Args<Off>& a, const Tuning& tu, int cgrid, 
                                hipStream_t st) {
   (void)hipEventRecord(ev[0], st);
   hipLaunchKernelGGL((k_compact<false, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, 0);
-  (void)hipEventRecord(ev[1], st);
-  hipLaunchKernelGGL((k_big<false, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, 0, collect);
-  (void)hipEventRecord(ev[2], st);
-  hipLaunchKernelGGL((k_round<kBlock, false, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, 0, collect);
-  (void)hipEventRecord(ev[3], st);
+  launch_updates<false, BATCH, Off>(a, tu, 0, collect, st, ev + 1);
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a.ctl, 1);
 }
 
@@ -326,11 +340,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, st, ws->ctl);
   hipLaunchKernelGGL(k_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, r0, tu.t0, tu.t1, tu.t2);
   hipLaunchKernelGGL((k_compact<true, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, 0);
-  if (timing) KC_HIP(hipEventRecord(ev[1], st));
-  hipLaunchKernelGGL((k_big<true, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, 0, collect);
-  if (timing) KC_HIP(hipEventRecord(ev[2], st));
-  hipLaunchKernelGGL((k_round<kBlock, true, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, 0, collect);
-  if (timing) KC_HIP(hipEventRecord(ev[3], st));
+  launch_updates<true, BATCH, Off>(a, tu, 0, collect, st, timing ? ev + 1 : nullptr);
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, ws->ctl, 1);
   KC_HIP(hipGetLastError());
   unsigned long long prev[KI_COUNT][kLaneStats];
@@ -370,8 +380,8 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     KC_HIP(hipStreamSynchronize(st));
     init_ms = elapsed(ev[0], ev[1]);
-    kms[KCORE_K_BIG_FIRST] = elapsed(ev[1], ev[2]);
-    kms[KCORE_K_ROUND_FIRST] = elapsed(ev[2], ev[3]);
+    kms[KCORE_K_BIG_FIRST] = kBigFirst ? elapsed(ev[1], ev[2]) : elapsed(ev[2], ev[3]);
+    kms[KCORE_K_ROUND_FIRST] = kBigFirst ? elapsed(ev[2], ev[3]) : elapsed(ev[1], ev[2]);
     if (trace_env)
       std::fprintf(stderr, "[kcore-trace] n=%lld nnz=%lld pop=%d/%d/%d/%d init_ms=%.3f\n", (long long)n,
                    (long long)nnz, ws->host_ctl->pop[0], ws->host_ctl->pop[1], ws->host_ctl->pop[2],
@@ -407,8 +417,8 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
       for (int i = 0; i < K; ++i) {
         hipEvent_t* e = ev + kRoundEvents * i;
         kms[KCORE_K_COMPACT] += elapsed(e[0], e[1]);
-        kms[KCORE_K_BIG] += elapsed(e[1], e[2]);
-        kms[KCORE_K_ROUND] += elapsed(e[2], e[3]);
+        kms[KCORE_K_BIG] += kBigFirst ? elapsed(e[1], e[2]) : elapsed(e[2], e[3]);
+        kms[KCORE_K_ROUND] += kBigFirst ? elapsed(e[2], e[3]) : elapsed(e[1], e[2]);
         if (trace) trace_line(h, r - 1, "", elapsed(e[0], e[3]));
       }
     }
@@ -780,8 +790,7 @@ kcore_status serve_step(ServeArena* A, int32_t rounds, int32_t nslots, int32_t* 
   auto enqueue = [&]() {
     for (int i = 0; i < rounds; ++i) {
       hipLaunchKernelGGL((k_compact<false, int64_t>), dim3(cgrid), dim3(kBlock), 0, st, a, i);
-      hipLaunchKernelGGL((k_big<false, true, int64_t>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, i, 0);
-      hipLaunchKernelGGL((k_round<kBlock, false, true, int64_t>), dim3(tu.grid), dim3(kBlock), 0, st, a, i, 0);
+      launch_updates<false, true, int64_t>(a, tu, i, 0, st, nullptr);
     }
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a.ctl, rounds);
   };

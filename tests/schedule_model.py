@@ -12,10 +12,11 @@ writes and atomics of all vertices of a round interleaved at random:
 * a change from e to h makes neighbour v (estimate x as read) a candidate when
   x > h; in the first round every candidate is activated (one-sided rule);
   later, v is re-activated if it is updated in the same kernel of this round,
-  skipped if it is small and updated after the class-3 kernel, and otherwise
+  skipped if it is updated by the kernel that runs after the current one, and otherwise
   charged against its slack when x <= e (the two-sided rule), activated when
   the slack goes negative;
-* class-3 vertices (degree above `big_deg`) run before the others in a round.
+* class-3 vertices (degree above `big_deg`) run before the others in a round
+  (after them with big_first=False).
 
 `rule` selects deliberate mistakes, so that tests can show the model would
 notice them: "no_frontier_clause" drops the re-activation of same-kernel
@@ -34,7 +35,8 @@ def _hindex(vals, cap):
     return min(h, cap)
 
 
-def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_rounds: int = 10_000):
+def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_rounds: int = 10_000,
+              big_first: bool = True):
     """Coreness of the graph (adjacency lists) under one random schedule; returns (estimates, rounds)."""
     est = [len(adj[u]) for u in range(n)]
     big = [len(adj[u]) > big_deg for u in range(n)]
@@ -68,8 +70,8 @@ def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_r
                     act = True
                 elif stamp[v] == r and big[v] == cur_big and rule != "no_frontier_clause":
                     act = True
-                elif stamp[v] == r and cur_big and not big[v]:
-                    act = False
+                elif stamp[v] == r and cur_big == big_first:
+                    act = False  # v is updated by the kernel that runs after the current one
                 elif x <= e:
                     old = slack[v]
                     slack[v] = old - 1
@@ -82,7 +84,7 @@ def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_r
         rounds += 1
         if rounds > max_rounds:
             raise RuntimeError("model did not converge")
-        phases = [None] if rule == "no_kernel_order" else [True, False]
+        phases = [None] if rule == "no_kernel_order" else [big_first, not big_first]
         for ph in phases:
             gens = [proc(u, big[u]) for u in frontier if ph is None or big[u] == ph]
             live = list(range(len(gens)))

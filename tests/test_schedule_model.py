@@ -26,11 +26,12 @@ def graphs(count, seed):
 CASES = graphs(1500, seed=11)
 
 
-def test_model_reaches_the_coreness_under_random_schedules():
+@pytest.mark.parametrize("big_first", [True, False])
+def test_model_reaches_the_coreness_under_random_schedules(big_first):
     rng = random.Random(5)
     for n, adj, ref in CASES:
         for big_deg in (rng.randint(1, 8), 1 << 30):
-            got, _ = run_model(n, adj, rng, big_deg)
+            got, _ = run_model(n, adj, rng, big_deg, big_first=big_first)
             assert got == ref, (n, adj, big_deg)
 
 
