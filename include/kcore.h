@@ -68,7 +68,12 @@ typedef struct kcore_tuning {
                               single-workgroup tail is off) and leave the estimates reached so far in
                               out_core: an upper bound of the coreness, equal to it once the run has
                               converged.  Instrumentation of the convergence; 0: run to the fixpoint */
-  int32_t reserved[3];
+  int32_t relabel;         /* single-graph calls: 2 renumbers the vertices by decreasing degree on the device
+                              before the decomposition (the estimates of high-degree vertices then share cache
+                              lines; the renumbering itself costs about one sweep of random reads, so it pays
+                              only on some graphs); 0 or 1: no renumbering.  Results come back in the caller's
+                              numbering */
+  int32_t reserved[2];
 } kcore_tuning;
 
 /* Round kernels, as indices into kcore_stats.kernel.  The first round (every
@@ -126,7 +131,9 @@ typedef struct kcore_stats {
  *   stream    hipStream_t (as void*), NULL for the default stream.
  * All graph buffers are owned by the caller and only read.  The library keeps
  * a per-device workspace (29 bytes per vertex plus 4 bytes per adjacency
- * entry for the pruned neighbour lists, and a small control block),
+ * entry for the pruned neighbour lists, and a small control block; a graph
+ * that is renumbered by degree (kcore_tuning.relabel) adds 45 bytes per vertex
+ * and 4 per entry for its renumbered copy),
  * allocated on first use, grown on demand and reused by later calls.
  * Work is enqueued on `stream`; the call returns after the fixpoint has been
  * reached (it synchronises `stream` a few times to test for convergence), so

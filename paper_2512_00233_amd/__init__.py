@@ -50,7 +50,8 @@ class Tuning(ctypes.Structure):
         ("no_prune", ctypes.c_int32),
         ("no_graph", ctypes.c_int32),
         ("max_rounds", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("relabel", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 

@@ -1085,11 +1085,13 @@ __global__ __launch_bounds__(256) void k_init(Args<Off> a, int32_t r0, int32_t t
 // Build class lists from a per-vertex predicate: SEED = the first-round lists
 // (every vertex of degree >= 2, into slist / seed_fill), otherwise the lists of
 // a round whose appends overflowed (stamp == round, into ccnt).  Each workgroup
-// owns a contiguous vertex range split among its wavefronts: a counting pass,
-// one atomic per workgroup and class, a writing pass without barriers.
+// owns a contiguous vertex range split among its wavefronts, read in pieces of
+// kCompactPerLane vertices per lane with every load of a piece in flight at
+// once: a counting pass, one atomic per workgroup and class, then a writing
+// pass over the same range.
 template <bool SEED, typename Off>
 __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
-  constexpr int BLOCK = 256, NW = BLOCK / kWave;
+  constexpr int BLOCK = 256, NW = BLOCK / kWave, P = kCompactPerLane, PIECE = kWave * P;
   __shared__ int32_t wcnt[NW][kClasses];
   __shared__ int32_t bbase[kClasses];
   Ctl* ctl = a.ctl;
@@ -1097,19 +1099,31 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
   if (!SEED && ctl->overflow[round % 3][0] == 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int64_t n = a.gact ? (int64_t)ctl->nhi : a.n;  // served graphs: the range of the live slots
-  const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + kWave * NW - 1) / (kWave * NW) * (kWave * NW);
+  const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + PIECE * NW - 1) / (PIECE * NW) * (PIECE * NW);
   const int64_t wchunk = chunk / NW;
   const int64_t w0 = (int64_t)blockIdx.x * chunk + wave * wchunk, w1 = min(n, w0 + wchunk);
-  auto cls_if_active = [&](int64_t v) -> int {
-    if (v >= w1) return kClasses;
-    const bool act = SEED ? a.est[v] >= 2 : a.stamp[v] == round;
-    return act ? (int)a.cls[v] : kClasses;
+  // class of each vertex of a piece (kClasses: not in the list)
+  auto piece = [&](int64_t pb, int32_t (&c)[P]) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int64_t v = pb + i * kWave + lane;
+      c[i] = v < w1 ? (SEED ? a.est[v] : a.stamp[v]) : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int64_t v = pb + i * kWave + lane;
+      const bool act = SEED ? c[i] >= 2 : c[i] == round;
+      c[i] = act ? (int32_t)a.cls[v] : kClasses;
+    }
   };
   int32_t mine[kClasses] = {0, 0, 0, 0};
-  for (int64_t vb = w0; vb < w1; vb += kWave) {
-    const int c = cls_if_active(vb + lane);
+  for (int64_t pb = w0; pb < w1; pb += PIECE) {
+    int32_t c[P];
+    piece(pb, c);
 #pragma unroll
-    for (int k = 0; k < kClasses; ++k) mine[k] += c == k;
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+      for (int k = 0; k < kClasses; ++k) mine[k] += c[i] == k;
   }
 #pragma unroll
   for (int k = 0; k < kClasses; ++k) {
@@ -1134,14 +1148,18 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
     pos[k] = rb[k] + bbase[k] + before;
   }
   int32_t* out = SEED ? a.slist : list_of(a, round);
-  for (int64_t vb = w0; vb < w1; vb += kWave) {
-    const int64_t v = vb + lane;
-    const int c = cls_if_active(v);
+  for (int64_t pb = w0; pb < w1; pb += PIECE) {
+    int32_t c[P];
+    piece(pb, c);
 #pragma unroll
-    for (int k = 0; k < kClasses; ++k) {
-      const uint64_t m = ballot(c == k);
-      if (c == k) out[pos[k] + lanes_below(m)] = (int32_t)v;
-      pos[k] += popc(m);
+    for (int i = 0; i < P; ++i) {
+      const int64_t v = pb + i * kWave + lane;
+#pragma unroll
+      for (int k = 0; k < kClasses; ++k) {
+        const uint64_t m = ballot(c[i] == k);
+        if (c[i] == k) out[pos[k] + lanes_below(m)] = (int32_t)v;
+        pos[k] += popc(m);
+      }
     }
   }
 }
@@ -1364,6 +1382,88 @@ __global__ void k_serve_reset(Ctl* ctl, int32_t r0) {
   for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / sizeof(int32_t)); i += blockDim.x) p[i] = 0;
   __syncthreads();
   if (threadIdx.x == 0) ctl->rbase = r0;
+}
+
+// ------------------------------------------------------------------ degree relabelling
+// On request, a graph is renumbered by decreasing degree (in buckets of
+// kRelabelBuckets degrees, stable) before the decomposition, so that the
+// estimates of the high-degree vertices, which most adjacency entries of a
+// skewed graph point to, share cache lines.
+
+// Rows of degree above kRelabelLongDeg (they come first after the renumbering) and their entries.
+template <typename Off>
+__global__ __launch_bounds__(256) void k_relabel_probe(int64_t n, const Off* row_ptr,
+                                                       unsigned long long* out /* [2] */) {
+  unsigned long long rows = 0, entries = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = (int64_t)(row_ptr[v + 1] - row_ptr[v]);
+    if (d > kRelabelLongDeg) {
+      rows += 1;
+      entries += (unsigned long long)d;
+    }
+  }
+  rows = wave_sum(rows);
+  entries = wave_sum(entries);
+  if (lane_id() == 0 && (rows || entries)) {
+    atomicAdd(&out[0], rows);
+    atomicAdd(&out[1], entries);
+  }
+}
+
+// Sort keys (smaller key = larger degree bucket) and the identity permutation.
+template <typename Off>
+__global__ __launch_bounds__(256) void k_relabel_keys(int64_t n, const Off* row_ptr, uint32_t* keys, int32_t* ids) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = (int64_t)(row_ptr[v + 1] - row_ptr[v]);
+    keys[v] = (uint32_t)(kRelabelBuckets - 1 - min(d, (int64_t)kRelabelBuckets - 1));
+    ids[v] = (int32_t)v;
+  }
+}
+
+// new_of[order[i]] = i, and the degree of every new row.
+template <typename Off>
+__global__ __launch_bounds__(256) void k_relabel_inverse(int64_t n, const Off* row_ptr, const int32_t* order,
+                                                         int32_t* new_of, int64_t* new_deg) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i == n) {
+      new_deg[n] = 0;
+      continue;
+    }
+    const int32_t u = order[i];
+    new_of[u] = (int32_t)i;
+    new_deg[i] = (int64_t)(row_ptr[u + 1] - row_ptr[u]);
+  }
+}
+
+// Rows [0, nlong) (the long ones come first) are copied by one wavefront each,
+// the others by one lane each; entries are renamed through new_of.
+template <typename Off>
+__global__ __launch_bounds__(256) void k_relabel_rows(int64_t n, int64_t nlong, const Off* row_ptr,
+                                                      const int32_t* col, const int32_t* order,
+                                                      const int32_t* new_of, const int64_t* nrp, int32_t* ncol) {
+  const int lane = lane_id();
+  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t i = gw; i < nlong; i += nw) {
+    const int32_t u = order[i];
+    const Off b = row_ptr[u];
+    const int64_t d = (int64_t)(row_ptr[u + 1] - b), o = nrp[i];
+    for (int64_t j = lane; j < d; j += kWave) ncol[o + j] = new_of[col[b + j]];
+  }
+  for (int64_t i = nlong + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = order[i];
+    const Off b = row_ptr[u];
+    const int64_t d = (int64_t)(row_ptr[u + 1] - b), o = nrp[i];
+    for (int64_t j = 0; j < d; ++j) ncol[o + j] = new_of[col[b + j]];
+  }
+}
+
+// Results back to the caller's numbering.
+__global__ __launch_bounds__(256) void k_relabel_out(int64_t n, const int32_t* new_of, const int32_t* est_new,
+                                                     int32_t* out) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    out[v] = est_new[new_of[v]];
 }
 
 }  // namespace kcore

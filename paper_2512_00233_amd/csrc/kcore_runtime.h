@@ -27,6 +27,7 @@ struct Tuning {
   int prune;      // pruned adjacency on/off
   int use_graph;  // capture chunks of round launches as hipGraphs
   int max_rounds; // > 0: stop after this many rounds (tail off)
+  int relabel;    // 1: renumber by degree first (single-graph calls)
 };
 
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus);

@@ -2,6 +2,7 @@
 // (first round over every vertex, later rounds enqueued in chunks, convergence
 // polled on a pinned copy of the device control block) and argument checking.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstdio>
@@ -55,6 +56,22 @@ struct Workspace {
   int32_t* host_verr = nullptr;  // pinned
   int64_t* host_nnz = nullptr;   // pinned
   int32_t epoch = 1;
+  // degree relabelling (single-graph calls on skewed graphs)
+  struct Relabel {
+    int64_t cap_n = 0, cap_nnz = 0;
+    uint32_t* keys[2] = {nullptr, nullptr};
+    int32_t* ids = nullptr;
+    int32_t* order = nullptr;
+    int32_t* new_of = nullptr;
+    int64_t* new_deg = nullptr;
+    int64_t* nrp = nullptr;
+    int32_t* ncol = nullptr;
+    int32_t* nout = nullptr;
+    void* temp = nullptr;
+    size_t temp_bytes = 0;
+    unsigned long long* probe = nullptr;       // device [2]
+    unsigned long long* host_probe = nullptr;  // pinned [2]
+  } rl;
   std::vector<hipEvent_t> events;  // timing mode: one pair per round launch
   struct GraphEntry {
     std::string key;
@@ -77,8 +94,20 @@ struct Workspace {
     return KCORE_OK;
   }
 
+  void release_relabel() {
+    for (void* p : {(void*)rl.keys[0], (void*)rl.keys[1], (void*)rl.ids, (void*)rl.order, (void*)rl.new_of,
+                    (void*)rl.new_deg, (void*)rl.nrp, (void*)rl.ncol, (void*)rl.nout, rl.temp})
+      if (p) (void)hipFree(p);
+    unsigned long long* probe = rl.probe;
+    unsigned long long* host_probe = rl.host_probe;
+    rl = Relabel();
+    rl.probe = probe;
+    rl.host_probe = host_probe;
+  }
+
   void release() {
     drop_graphs();
+    release_relabel();
     for (void* p : {(void*)stamp, (void*)cls, (void*)lists[0], (void*)lists[1], (void*)slist, (void*)plen,
                     (void*)plow, (void*)vbase, (void*)slack, (void*)pruned})
       (void)hipFree(p);
@@ -163,6 +192,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.prune = 1;
   r.use_graph = 1;
   r.max_rounds = 0;
+  r.relabel = 0;
   if (const char* e = std::getenv("KCORE_TAIL")) r.tail = std::atoi(e);
   if (t) {
     if (t->thread_max_deg > 0) r.t0 = std::min(t->thread_max_deg, kLaneMaxDeg);
@@ -178,6 +208,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
     if (t->list_cap > 0) r.list_cap = t->list_cap;
     r.prune = t->no_prune != 1;
     r.use_graph = t->no_graph != 1;
+    r.relabel = t->relabel == 2;
     if (t->max_rounds > 0) {
       r.max_rounds = t->max_rounds;
       r.tail = 0;
@@ -198,6 +229,13 @@ static bool env_flag(const char* name) {
 
 // ------------------------------------------------------------------ driver
 constexpr int kBlock = 256;
+
+// Workgroups of the compaction kernel: at least 4 pieces of kCompactPerLane
+// vertices per lane each, at most two per compute unit (few counter atomics).
+static int compact_grid(int64_t n, int num_cus) {
+  const int64_t per_block = (int64_t)kBlock * kCompactPerLane * 4;
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + per_block - 1) / per_block, 2 * (int64_t)num_cus));
+}
 
 // The two update kernels of a round (slot relative to the round base), in
 // kBigFirst order.  With ev (3 events) the launches are bracketed: ev[0]
@@ -296,7 +334,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
                                int32_t* out, const Tuning& tu, kcore_stats* stats, hipStream_t st,
                                std::vector<kcore_round_record>* rec = nullptr) {
   const int init_grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
-  const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, (int64_t)ws->num_cus * 8));
+  const int cgrid = compact_grid(n, ws->num_cus);
   if (ws->epoch > (1 << 29)) {
     KC_HIP(hipMemsetAsync(ws->stamp, 0, sizeof(int32_t) * ws->cap_n, st));
     ws->epoch = 1;
@@ -482,6 +520,89 @@ static kcore_status validate_csr(Workspace* ws, int64_t n, const Off* row_ptr, c
   return KCORE_OK;
 }
 
+// Buffers of the relabelled copy (grown on demand).
+static kcore_status ensure_relabel(Workspace* ws, int64_t n, int64_t nnz, hipStream_t st) {
+  auto& rl = ws->rl;
+  if (!rl.probe) {
+    KC_HIP(hipMalloc(&rl.probe, 2 * sizeof(unsigned long long)));
+    KC_HIP(hipHostMalloc(&rl.host_probe, 2 * sizeof(unsigned long long), hipHostMallocDefault));
+  }
+  if (n <= rl.cap_n && nnz <= rl.cap_nnz) return KCORE_OK;
+  KC_HIP(hipStreamSynchronize(st));
+  const int64_t cn = std::max(n, rl.cap_n), ce = std::max<int64_t>({nnz, rl.cap_nnz, 1});
+  ws->release_relabel();
+  size_t sort_bytes = 0, scan_bytes = 0;
+  KC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                            (int32_t*)nullptr, (int32_t*)nullptr, (int)cn, 0, 10, st));
+  KC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (int64_t*)nullptr, (int64_t*)nullptr, (int)(cn + 1),
+                                          st));
+  rl.temp_bytes = std::max<size_t>({sort_bytes, scan_bytes, 256});
+  const bool ok = hipMalloc(&rl.keys[0], sizeof(uint32_t) * cn) == hipSuccess &&
+                  hipMalloc(&rl.keys[1], sizeof(uint32_t) * cn) == hipSuccess &&
+                  hipMalloc(&rl.ids, sizeof(int32_t) * cn) == hipSuccess &&
+                  hipMalloc(&rl.order, sizeof(int32_t) * cn) == hipSuccess &&
+                  hipMalloc(&rl.new_of, sizeof(int32_t) * cn) == hipSuccess &&
+                  hipMalloc(&rl.new_deg, sizeof(int64_t) * (cn + 1)) == hipSuccess &&
+                  hipMalloc(&rl.nrp, sizeof(int64_t) * (cn + 1)) == hipSuccess &&
+                  hipMalloc(&rl.ncol, sizeof(int32_t) * ce) == hipSuccess &&
+                  hipMalloc(&rl.nout, sizeof(int32_t) * cn) == hipSuccess &&
+                  hipMalloc(&rl.temp, rl.temp_bytes) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    ws->release_relabel();
+    return fail(KCORE_E_NOMEM, "relabel buffers: allocation failed");
+  }
+  rl.cap_n = cn;
+  rl.cap_nnz = ce;
+  return KCORE_OK;
+}
+
+// Rows of degree > kRelabelLongDeg and the entries in them (synchronises the stream).
+template <typename Off>
+static kcore_status relabel_probe(Workspace* ws, int64_t n, const Off* row_ptr, int64_t* rows, int64_t* entries,
+                                  hipStream_t st) {
+  kcore_status s = ensure_relabel(ws, 0, 0, st);
+  if (s != KCORE_OK) return s;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 8));
+  KC_HIP(hipMemsetAsync(ws->rl.probe, 0, 2 * sizeof(unsigned long long), st));
+  hipLaunchKernelGGL(k_relabel_probe<Off>, dim3(grid), dim3(kBlock), 0, st, n, row_ptr, ws->rl.probe);
+  KC_HIP(hipGetLastError());
+  KC_HIP(hipMemcpyAsync(ws->rl.host_probe, ws->rl.probe, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  KC_HIP(hipStreamSynchronize(st));
+  *rows = (int64_t)ws->rl.host_probe[0];
+  *entries = (int64_t)ws->rl.host_probe[1];
+  return KCORE_OK;
+}
+
+// Decomposition of the graph renumbered by decreasing degree; results in the caller's numbering.
+template <typename Off>
+static kcore_status decompose_relabelled(Workspace* ws, int64_t n, int64_t nnz, const Off* row_ptr,
+                                         const int32_t* col, int32_t* out, int64_t nlong, const Tuning& tu,
+                                         kcore_stats* stats, hipStream_t st, std::vector<kcore_round_record>* rec) {
+  kcore_status s = ensure_relabel(ws, n, nnz, st);
+  if (s != KCORE_OK) return s;
+  auto& rl = ws->rl;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16));
+  hipLaunchKernelGGL(k_relabel_keys<Off>, dim3(grid), dim3(kBlock), 0, st, n, row_ptr, rl.keys[0], rl.ids);
+  KC_HIP(hipGetLastError());
+  size_t bytes = rl.temp_bytes;
+  KC_HIP(hipcub::DeviceRadixSort::SortPairs(rl.temp, bytes, rl.keys[0], rl.keys[1], rl.ids, rl.order, (int)n, 0,
+                                            10, st));
+  hipLaunchKernelGGL(k_relabel_inverse<Off>, dim3(grid), dim3(kBlock), 0, st, n, row_ptr, rl.order, rl.new_of,
+                     rl.new_deg);
+  KC_HIP(hipGetLastError());
+  bytes = rl.temp_bytes;
+  KC_HIP(hipcub::DeviceScan::ExclusiveSum(rl.temp, bytes, rl.new_deg, rl.nrp, (int)(n + 1), st));
+  hipLaunchKernelGGL(k_relabel_rows<Off>, dim3(grid), dim3(kBlock), 0, st, n, nlong, row_ptr, col, rl.order,
+                     rl.new_of, rl.nrp, rl.ncol);
+  KC_HIP(hipGetLastError());
+  s = run_rounds<false, int64_t>(ws, n, nnz, rl.nrp, rl.ncol, rl.nout, tu, stats, st, rec);
+  if (s != KCORE_OK) return s;
+  hipLaunchKernelGGL(k_relabel_out, dim3(grid), dim3(kBlock), 0, st, n, rl.new_of, rl.nout, out);
+  KC_HIP(hipGetLastError());
+  return KCORE_OK;
+}
+
 template <typename Off>
 static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t* col, int32_t* out,
                                    const kcore_tuning* tuning, kcore_stats* stats, hipStream_t st,
@@ -506,6 +627,12 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
     if (s != KCORE_OK) return s;
   }
   const Tuning tu = resolve_tuning(tuning, ws->num_cus);
+  if (tu.relabel && n > 1 && n < INT32_MAX - 1 && nnz > 0) {
+    int64_t long_rows = 0, long_entries = 0;
+    s = relabel_probe<Off>(ws, n, row_ptr, &long_rows, &long_entries, st);
+    if (s != KCORE_OK) return s;
+    return decompose_relabelled<Off>(ws, n, nnz, row_ptr, col, out, long_rows, tu, stats, st, rec);
+  }
   return run_rounds<false, Off>(ws, n, nnz, row_ptr, col, out, tu, stats, st, rec);
 }
 
@@ -786,7 +913,7 @@ kcore_status serve_step(ServeArena* A, int32_t rounds, int32_t nslots, int32_t* 
   hipStream_t st = (hipStream_t)stream;
   const Args<int64_t> a = serve_args(A);
   const Tuning& tu = A->tu;
-  const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((A->nv + 4095) / 4096, (int64_t)A->num_cus * 8));
+  const int cgrid = compact_grid(A->nv, A->num_cus);
   auto enqueue = [&]() {
     for (int i = 0; i < rounds; ++i) {
       hipLaunchKernelGGL((k_compact<false, int64_t>), dim3(cgrid), dim3(kBlock), 0, st, a, i);

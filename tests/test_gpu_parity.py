@@ -164,6 +164,8 @@ TUNINGS = {
     "never_compact": dict(list_cap=1 << 30),
     "no_prune": dict(no_prune=1),
     "no_prune_one_sided": dict(no_prune=1, activation=1, list_cap=64),
+    "relabel_always": dict(relabel=2),
+    "relabel_always_no_tail": dict(relabel=2, tail_threshold=-1, list_cap=256),
 }
 
 
@@ -177,6 +179,20 @@ def test_results_do_not_depend_on_tuning(tname):
         got = run_gpu(g.row_ptr, g.col_idx, tuning=t, stats=st)
         assert np.array_equal(got, oracle.coreness(g.row_ptr, g.col_idx)), (tname, name)
         assert st.rounds >= 1
+
+
+def test_relabel_on_degenerate_and_int32_rows():
+    kc_ = kc()
+    t = kc_.Tuning(relabel=2)
+    # star (one long row), a clique (all rows equal), isolated vertices, int32 row offsets
+    for n, edges in [sg.star(3000), sg.complete(70), (50, [])]:
+        rp, ci = sg.to_csr(n, edges)
+        assert np.array_equal(run_gpu(rp, ci, tuning=t), oracle.coreness(rp, ci))
+    g = gg.workload("er_small")
+    dev = torch.device("cuda:0")
+    out = kc_.decompose(torch.from_numpy(g.row_ptr.astype(np.int64)).to(dev), torch.from_numpy(g.col_idx).to(dev),
+                        tuning=t)
+    assert np.array_equal(out.cpu().numpy(), oracle.coreness(g.row_ptr, g.col_idx))
 
 
 def test_workspace_reuse_across_sizes():
