@@ -74,11 +74,14 @@ def kernel_bytes(k, off_bytes=8):
 
 
 def run_workload(name, steps, warmup, torch, kc, gg, roofline_runs=3):
+    import numpy as np
     """Plain path on one resident graph: instrumented passes (per-kernel HIP events and
     work counters, for the roofline), then `warmup` and `steps` timed decompositions."""
     g = gg.workload(name)
     dev = torch.device("cuda:0")
-    rp = torch.from_numpy(g.row_ptr).to(dev)
+    # the small ER workload is specified with int32 row offsets (kcore_decompose32)
+    rp_host = g.row_ptr.astype(np.int32) if name == "er_small" else g.row_ptr
+    rp = torch.from_numpy(rp_host).to(dev)
     ci = torch.from_numpy(g.col_idx).to(dev)
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()

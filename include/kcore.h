@@ -151,6 +151,10 @@ kcore_status kcore_decompose32(int64_t n, const int32_t* row_ptr, const int32_t*
 kcore_status kcore_decompose_ex(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
                                 const kcore_tuning* tuning, kcore_stats* stats, void* stream);
 
+/* The same with int32 row offsets. */
+kcore_status kcore_decompose32_ex(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
+                                  const kcore_tuning* tuning, kcore_stats* stats, void* stream);
+
 /* One round of a run recorded by kcore_decompose_rounds. */
 typedef struct kcore_round_record {
   int32_t round;           /* 1 = the first round (every vertex of degree >= 2) */

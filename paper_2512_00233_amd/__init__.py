@@ -190,6 +190,8 @@ def load():
     lib.kcore_decompose.argtypes = [i64, vp, vp, vp, vp]
     lib.kcore_decompose32.restype = i32
     lib.kcore_decompose32.argtypes = [i64, vp, vp, vp, vp]
+    lib.kcore_decompose32_ex.restype = i32
+    lib.kcore_decompose32_ex.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats), vp]
     lib.kcore_decompose_ex.restype = i32
     lib.kcore_decompose_ex.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats), vp]
     lib.kcore_decompose_rounds.restype = i32
@@ -270,9 +272,12 @@ def decompose(row_ptr, col_idx, out=None, tuning: Tuning | None = None, stats: S
     col_ptr = col_idx.data_ptr() if col_idx.numel() else out.data_ptr()  # any valid pointer when nnz == 0
     st = _stream_handle(stream)
     if row_ptr.dtype == torch.int32:
-        if tuning is not None or stats is not None:
-            raise ValueError("tuning/stats are available with int64 row_ptr only")
-        _check(lib.kcore_decompose32(n, row_ptr.data_ptr(), col_ptr, out.data_ptr(), st))
+        if tuning is None and stats is None:
+            _check(lib.kcore_decompose32(n, row_ptr.data_ptr(), col_ptr, out.data_ptr(), st))
+        else:
+            _check(lib.kcore_decompose32_ex(n, row_ptr.data_ptr(), col_ptr, out.data_ptr(),
+                                            ctypes.byref(tuning) if tuning is not None else None,
+                                            ctypes.byref(stats) if stats is not None else None, st))
     elif tuning is None and stats is None:
         _check(lib.kcore_decompose(n, row_ptr.data_ptr(), col_ptr, out.data_ptr(), st))
     else:

@@ -981,6 +981,11 @@ kcore_status kcore_decompose_ex(int64_t n, const int64_t* row_ptr, const int32_t
   return decompose_impl<int64_t>(n, row_ptr, col_idx, out_core, tuning, stats, (hipStream_t)stream);
 }
 
+kcore_status kcore_decompose32_ex(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
+                                  const kcore_tuning* tuning, kcore_stats* stats, void* stream) {
+  return decompose_impl<int32_t>(n, row_ptr, col_idx, out_core, tuning, stats, (hipStream_t)stream);
+}
+
 kcore_status kcore_decompose_rounds(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
                                     const kcore_tuning* tuning, kcore_round_record* records, int32_t max_records,
                                     int32_t* n_records, void* stream) {

@@ -119,6 +119,9 @@ def test_er_small_int32_and_int64_rows():
     a = assert_parity("er_small/int64", g.row_ptr, g.col_idx)
     b = run_gpu(g.row_ptr, g.col_idx, int32_rows=True)
     assert np.array_equal(a, b)
+    st = kc().Stats()
+    c = run_gpu(g.row_ptr, g.col_idx, int32_rows=True, tuning=kc().Tuning(no_graph=1), stats=st)
+    assert np.array_equal(a, c) and st.rounds >= 1 and st.edge_visits > 0
 
 
 @pytest.mark.parametrize("name", ["road_512", "rmat16", "rmat20"])
