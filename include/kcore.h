@@ -281,8 +281,9 @@ typedef struct kcore_serve_report {
   int64_t reserved[4];
 } kcore_serve_report;
 
-/* Create a server (cfg may be NULL: defaults).  Allocates the arenas, three
- * HIP streams of default priority and the server thread.  KCORE_E_NOMEM when
+/* Create a server (cfg may be NULL: defaults).  Allocates the arenas, four
+ * HIP streams of default priority (compute, two for uploads, one for results)
+ * and the server thread.  KCORE_E_NOMEM when
  * the budget cannot be allocated. */
 kcore_status kcore_serve_create(const kcore_serve_config* cfg, kcore_server** out);
 

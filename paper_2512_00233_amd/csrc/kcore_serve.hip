@@ -36,6 +36,7 @@
   } while (0)
 
 static_assert(kcore::kServeVertexBytes == KCORE_SERVE_VERTEX_BYTES, "vertex footprint out of date");
+constexpr int kUploadStreams = 2;
 static_assert(kcore::kServeEntryBytes == KCORE_SERVE_ENTRY_BYTES, "entry footprint out of date");
 
 namespace kcore {
@@ -157,7 +158,9 @@ struct kcore_server {
   int32_t max_slots = 0, max_queue = 0, rounds_per_step = 0;
   int64_t nv = 0, ne = 0;
   ServeArena arena;
-  hipStream_t cs = nullptr, up = nullptr, down = nullptr;
+  hipStream_t cs = nullptr, down = nullptr;
+  hipStream_t up[kUploadStreams] = {};  // uploads alternate between these (several copy engines)
+  int next_up = 0;
   hipEvent_t step_ev = nullptr;
   std::vector<hipEvent_t> spare_events;
   // pinned host buffers
@@ -302,15 +305,17 @@ struct kcore_server {
     }
     const double t = now_us();
     for (Request* r : taken) {
+      hipStream_t us = up[next_up];
+      next_up = (next_up + 1) % kUploadStreams;
       r->t_admit = t;
       r->st = St::Staging;
       r->ev = take_event();
       if (!r->ev) return fail(KCORE_E_HIP, "hipEventCreate failed");
       KC_HIP_RET(hipMemcpyAsync(arena.row_ptr + r->vb, r->row_ptr, sizeof(int64_t) * (r->n + 1),
-                                hipMemcpyHostToDevice, up));
+                                hipMemcpyHostToDevice, us));
       if (r->nnz > 0)
-        KC_HIP_RET(hipMemcpyAsync(arena.col + r->eb, r->col, sizeof(int32_t) * r->nnz, hipMemcpyHostToDevice, up));
-      KC_HIP_RET(hipEventRecord(r->ev, up));
+        KC_HIP_RET(hipMemcpyAsync(arena.col + r->eb, r->col, sizeof(int32_t) * r->nnz, hipMemcpyHostToDevice, us));
+      KC_HIP_RET(hipEventRecord(r->ev, us));
       staging.push_back(r);
     }
     return KCORE_OK;
@@ -435,7 +440,7 @@ struct kcore_server {
     }
     // drain the device, then cancel whatever is left
     (void)hipStreamSynchronize(cs);
-    (void)hipStreamSynchronize(up);
+    for (hipStream_t st : up) (void)hipStreamSynchronize(st);
     (void)hipStreamSynchronize(down);
     std::lock_guard<std::mutex> lk(mu);
     const int32_t status = fatal == KCORE_OK ? KCORE_E_CANCELLED : fatal;
@@ -470,7 +475,9 @@ kcore_status create_impl(const kcore_serve_config* cfg_in, kcore_server** out) {
   auto* S = new kcore_server();
   auto cleanup = [&](kcore_status s) {
     serve_arena_destroy(&S->arena);
-    for (hipStream_t st : {S->cs, S->up, S->down})
+    for (hipStream_t st : {S->cs, S->down})
+      if (st) (void)hipStreamDestroy(st);
+    for (hipStream_t st : S->up)
       if (st) (void)hipStreamDestroy(st);
     if (S->step_ev) (void)hipEventDestroy(S->step_ev);
     for (void* p : {S->host_ctl, (void*)S->host_status, (void*)S->host_slot_vb, (void*)S->host_slots})
@@ -497,8 +504,9 @@ kcore_status create_impl(const kcore_serve_config* cfg_in, kcore_server** out) {
   S->ne = nv * epv;
   kcore_status s = serve_arena_create(&S->arena, cfg.device, S->nv, S->ne, S->max_slots, &cfg.tuning, nullptr);
   if (s != KCORE_OK) return cleanup(s);
-  if (hipStreamCreateWithFlags(&S->cs, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&S->up, hipStreamNonBlocking) != hipSuccess ||
+  bool streams_ok = true;
+  for (hipStream_t& st : S->up) streams_ok = streams_ok && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+  if (!streams_ok || hipStreamCreateWithFlags(&S->cs, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&S->down, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&S->step_ev, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc(&S->host_ctl, serve_ctl_size(), hipHostMallocDefault) != hipSuccess ||
@@ -663,7 +671,8 @@ kcore_status kcore_serve_destroy(kcore_server* S) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(S->device);
   serve_arena_destroy(&S->arena);
-  for (hipStream_t st : {S->cs, S->up, S->down}) (void)hipStreamDestroy(st);
+  for (hipStream_t st : {S->cs, S->down}) (void)hipStreamDestroy(st);
+  for (hipStream_t st : S->up) (void)hipStreamDestroy(st);
   (void)hipEventDestroy(S->step_ev);
   for (hipEvent_t e : S->spare_events) (void)hipEventDestroy(e);
   for (void* p : {S->host_ctl, (void*)S->host_status, (void*)S->host_slot_vb, (void*)S->host_slots})
