@@ -12,7 +12,13 @@ Prints ONE JSON line.  Extra objects:
                 against the 8 TB/s HBM peak;
   cpu_baseline  the CPU oracle (definition-level peeling, one thread) timed on
                 this host on the same graph;
-  also          the other plain workloads (road / ER small) measured the same way.
+  also          the other plain workloads (road / ER small) measured the same
+                way, and reduced runs of the batched form (256 graphs against
+                one plain call per graph) and of the served form (1000
+                requests: saturated graphs/s, Poisson p50/p99, FIFO plain calls).
+
+--workload batch / serve run those forms at full size (2048 graphs; 2000
+requests over a pool of 64 graphs).
 """
 import argparse
 import hashlib
@@ -348,7 +354,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=64, help="serve: device arena budget (GiB)")
     ap.add_argument("--rounds-per-step", type=int, default=8, help="serve: rounds between step boundaries")
     ap.add_argument("--autotune", default="", help="batch workload: run the autotuner and save to this JSON")
-    ap.add_argument("--also", default="road,er_small", help="other plain workloads to report (comma list)")
+    ap.add_argument("--also", default="road,er_small,batch,serve",
+                    help="other workloads to report (comma list; batch and serve run reduced versions)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-runs", type=int, default=ROOFLINE_RUNS,
                     help="instrumented decompositions (per-kernel HIP events and counters)")
@@ -417,6 +424,24 @@ def main():
 
     also = []
     for name in [w for w in args.also.split(",") if w and w != args.workload]:
+        if name in ("batch", "serve"):
+            # reduced versions of the batched and served forms (full size: --workload batch / serve)
+            sub = argparse.Namespace(**vars(args))
+            sub.no_cpu_baseline, sub.autotune, sub.steps, sub.warmup = True, "", 3, 1
+            sub.graphs, sub.requests, sub.pool = 256, 1000, 32
+            if name == "batch":
+                r = run_batch_workload(sub, torch, kc, gg, np)
+                also.append({"workload": "batch", "graphs": sub.graphs, "value": r["value"], "unit": "graphs/s",
+                             "plain_graphs_per_s": r["plain"]["graphs_per_s"],
+                             "speedup_vs_plain": r["speedup_vs_plain"], "identical": r["batch_equals_plain"]})
+            else:
+                r = run_serve_workload(sub, torch, kc, gg, np)
+                also.append({"workload": "serve", "requests": sub.requests, "value": r["value"], "unit": "graphs/s",
+                             "fifo_graphs_per_s": r["fifo_plain"]["graphs_per_s"],
+                             "speedup_vs_fifo": r["speedup_vs_fifo"], "p50_ms": r["poisson"]["p50_ms"],
+                             "p99_ms": r["poisson"]["p99_ms"], "fifo_p99_ms": r["fifo_plain"]["p99_ms"],
+                             "exact": r["exact"]})
+            continue
         g2, _, st2, ms2, _, pk2 = run_workload(name, args.steps, args.warmup, torch, kc, gg, 1)
         also.append({"workload": name, "value": round(g2.nnz / 2 / (ms2 * 1e-3) / 1e9, 3), "unit": "GTEPS",
                      "ms_per_step": round(ms2, 4), "rounds": st2.rounds, "tail_rounds": st2.tail_rounds,
