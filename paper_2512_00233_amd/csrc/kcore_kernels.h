@@ -4,8 +4,8 @@
 // holds an estimate est[u], initially deg(u); a vertex of the frontier
 // recomputes h = max{k <= est[u] : |{v in N(u) : est[v] >= k}| >= k} (the
 // h-index of its neighbours' estimates, capped by its own) and lowers est[u]
-// to h.  A change activates neighbours for the next round (FastK's activation,
-// Sec. IV "Further Optimizations").  The run ends when the frontier is empty.
+// to h.  A change activates neighbours for the next round (the activation of
+// FastK, Sec. IV).  The run ends when the frontier is empty.
 //
 // GPU-specific choices (not from the paper):
 //  * Updates are written in place and read by other lanes without
@@ -14,11 +14,16 @@
 //    decrease and never drop below the coreness, so any mixture of old and new
 //    reads still yields a valid upper bound and the same fixed point.
 //  * Activation: when u drops from a to b, neighbour v (estimate x read in
-//    this round) is activated iff x > b and (x <= a, or v belongs to the
-//    current frontier).  The first clause is the paper's two-sided filter;
-//    the second covers the neighbours whose own value is still moving in this
-//    round, for which x may be stale.  One-sided mode (x > b only) is kept as
-//    an option and used in the first round, where every vertex is active.
+//    this round) matters only if x > b.  In the first round every such v is
+//    activated (one-sided; every vertex is active).  Later, the two-sided
+//    filter of the paper (x <= a: u was counted in v's support at v's level)
+//    is applied exactly, through v's support slack (support at its level minus
+//    the level, kept since v's last recomputation): v is activated only when
+//    the slack goes negative.  A neighbour updated in the same kernel of this
+//    round may have read u's old value and is re-activated; class 3 and the
+//    small classes are separate kernels in a fixed order, so a neighbour of
+//    the other group either reads u's new value later or has a final value
+//    already (activate_changed).  One-sided mode is kept as an option.
 //  * Frontier membership is a per-vertex round stamp (atomicMax dedup).  The
 //    frontier is processed as four lists by degree class (lane <= 8,
 //    16-lane group <= 64, wavefront <= 512, workgroup above).  Activations
@@ -30,7 +35,7 @@
 //    later passes split the remaining interval evenly.  Long adjacency lists
 //    use a one-pass LDS histogram instead.
 //  * Pruned adjacency: after a full scan that yields h, a vertex of degree
-//    > 64 keeps the neighbours whose estimate is >= L = 3h/4.  Estimates only
+//    > 64 keeps the neighbours whose estimate is >= L = h - h/4.  Estimates only
 //    decrease, so the pruned-away neighbours stay below L forever, and a
 //    search over the pruned list that finds h' >= L is exact; otherwise the
 //    vertex rescans its full adjacency and rebuilds the list.

@@ -97,8 +97,8 @@ __device__ __forceinline__ Sink make_sink(const Args<Off>& a, int32_t next_round
 // round (dense) and in one-sided mode every candidate with x > h is activated.
 // Winners of the round-stamp dedup (atomicMax) are appended to the list of
 // their degree class with one atomic per class per wavefront, unless the next
-// round already rebuilds its lists by compaction (then, in the first round,
-// the stamps are plain stores and the activation count includes repeats).
+// round already rebuilds its lists by compaction (then the stamps are plain
+// stores and the activation count includes repeats).
 // Loads and atomics of a lane are issued together at each step.  Every active
 // lane of the wavefront must call this.
 template <int N, bool BIG, typename Off>
@@ -151,6 +151,15 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
   for (int i = 0; i < N; ++i) p[i] = (sub >> i & 1u) ? atomicSub(&a.slack[v[i]], 1) : 1;
 #pragma unroll
   for (int i = 0; i < N; ++i) want |= ((sub >> i & 1u) && p[i] <= 0 ? 1u : 0u) << i;
+  if (compact_next) {
+    // the next round's lists come from the stamps: no dedup needed, plain stores
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (want >> i & 1u) a.stamp[v[i]] = s.stamp;
+    st.v[ST_ACTIVATIONS] += __popc(want);
+    if (a.gact && want) a.gact[gb] = s.stamp;
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < N; ++i) p[i] = (want >> i & 1u) ? atomicMax(&a.stamp[v[i]], s.stamp) : INT32_MAX;
   uint32_t first = 0;
@@ -159,7 +168,7 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
   st.v[ST_ACTIVATIONS] += __popc(first);
   // served graphs: the graph has work in the next round (all candidates share the current vertex's graph)
   if (a.gact && first) a.gact[gb] = s.stamp;
-  if (compact_next || !ballot(first != 0)) return;
+  if (!ballot(first != 0)) return;
 #pragma unroll
   for (int i = 0; i < N; ++i)
     p[i] = (first >> i & 1u) ? (cv[i] >= 0 ? cv[i] : (int32_t)a.cls[v[i]]) : kClasses;  // class of winners
