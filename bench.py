@@ -201,6 +201,7 @@ def run_batch_workload(args, torch, kc, gg, np):
         "data": "synthetic (seeded ER / Chung-Lu / lattice batch)",
         "config": {"workload": "batch", "graphs": G, "total_vertices": N, "total_entries": NNZ,
                    "rounds": st.rounds, "generation_s": round(gen_s, 1)},
+        "kernels_ms": {k: round(st.kernel[i].ms, 3) for i, k in enumerate(kc.KERNELS)},
         "plain": {"graphs_per_s": round(G / (ms_plain * 1e-3), 2), "ms_all_graphs": round(ms_plain, 3)},
         "speedup_vs_plain": round(ms_plain / ms_batch, 3),
         "batch_equals_plain": same,
