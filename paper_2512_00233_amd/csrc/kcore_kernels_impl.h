@@ -1107,7 +1107,7 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
   const int32_t round = ctl->rbase + slot;
   if (!SEED && ctl->overflow[round % 3][0] == 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
-  const int64_t n = a.gact ? (int64_t)ctl->nhi : a.n;  // served graphs: the range of the live slots
+  const int64_t n = a.served ? (int64_t)ctl->nhi : a.n;  // served graphs: the range of the live slots
   const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + PIECE * NW - 1) / (PIECE * NW) * (PIECE * NW);
   const int64_t wchunk = chunk / NW;
   const int64_t w0 = (int64_t)blockIdx.x * chunk + wave * wchunk, w1 = min(n, w0 + wchunk);

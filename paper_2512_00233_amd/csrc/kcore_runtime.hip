@@ -162,6 +162,7 @@ static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, bool 
             hipMalloc(&ws->plow, sizeof(int32_t) * cap) == hipSuccess &&
             hipMalloc(&ws->slack, sizeof(int32_t) * cap) == hipSuccess &&
             (!keep_vbase || hipMalloc(&ws->vbase, sizeof(int32_t) * cap) == hipSuccess) &&
+
             hipMalloc(&ws->pruned, sizeof(int32_t) * cap_e) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
@@ -256,6 +257,12 @@ static void launch_updates(const Args<Off>& a, const Tuning& tu, int32_t slot, i
   if (ev) (void)hipEventRecord(ev[2], st);
 }
 
+// The compaction of a round (a no-op unless its lists overflowed).
+template <typename Off>
+static void launch_compact(const Args<Off>& a, int cgrid, int32_t slot, hipStream_t st) {
+  hipLaunchKernelGGL((k_compact<false, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, slot);
+}
+
 // Launch one chunk of K rounds (slots 0..K-1 relative to ctl->rbase) and
 // advance the round base.  With use_graph the chunk is captured once per
 // launch shape and replayed.
@@ -264,7 +271,7 @@ static kcore_status launch_chunk(Workspace* ws, const Args<Off>& a, const Tuning
                                  int32_t collect, bool use_graph, hipStream_t st) {
   auto enqueue = [&]() {
     for (int i = 0; i < K; ++i) {
-      hipLaunchKernelGGL((k_compact<false, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, i);
+      launch_compact<Off>(a, cgrid, i, st);
       launch_updates<false, BATCH, Off>(a, tu, i, collect, st, nullptr);
     }
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a.ctl, K);
@@ -309,7 +316,7 @@ template <bool BATCH, typename Off>
 static void launch_round_timed(const Args<Off>& a, const Tuning& tu, int cgrid, int32_t collect, hipEvent_t* ev,
                                hipStream_t st) {
   (void)hipEventRecord(ev[0], st);
-  hipLaunchKernelGGL((k_compact<false, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, 0);
+  launch_compact<Off>(a, cgrid, 0, st);
   launch_updates<false, BATCH, Off>(a, tu, 0, collect, st, ev + 1);
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a.ctl, 1);
 }
@@ -360,7 +367,6 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   a.list_cap = tu.list_cap;
   a.one_sided = tu.one_sided;
   a.prune = tu.prune;
-  a.gact = nullptr;
   const int32_t collect = (stats || rec) ? 1 : 0;
   const bool trace_env = env_flag("KCORE_TRACE");
   const bool trace = trace_env || rec != nullptr;  // one round per launch, counters read after each
@@ -833,6 +839,7 @@ static Args<int64_t> serve_args(const ServeArena* A) {
   a.plow = A->plow;
   a.ctl = static_cast<Ctl*>(A->ctl);
   a.slack = A->slack;
+  a.served = 1;
   a.tail_threshold = A->tu.tail;
   a.list_cap = A->tu.list_cap;
   a.one_sided = A->tu.one_sided;
