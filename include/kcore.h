@@ -58,7 +58,8 @@ typedef struct kcore_tuning {
   int32_t grid_blocks;     /* workgroups per small-class round launch (0: 8 per compute unit) */
   int32_t big_grid_blocks; /* workgroups per class-3 round launch (0: 4 per compute unit) */
   int32_t rounds_per_poll; /* rounds enqueued before the first host check of the frontier */
-  int32_t activation;      /* 0: guarded two-sided rule (default), 1: one-sided rule */
+  int32_t activation;      /* 0: automatic (one-sided when the mean degree is below 4, else two-sided; the
+                              served form always uses two-sided), 1: one-sided rule, 2: two-sided rule */
   int32_t timing;          /* 1: bracket every kernel launch with HIP events (fills the ms statistics) */
   int32_t list_cap;        /* frontier list capacity per degree class; beyond it the next round rebuilds
                               its lists from the round stamps (0: library default 8192) */

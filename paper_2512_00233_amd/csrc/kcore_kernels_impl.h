@@ -1057,7 +1057,10 @@ __global__ void k_vbase(const int64_t* graph_vtx_off, int32_t* vbase) {
   for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) vbase[v] = (int32_t)v0;
 }
 
-// est = degree, degree class, class populations (one atomic per workgroup and class).
+// est = degree, degree class, class populations (one atomic per workgroup and
+// class).  A vertex of degree <= 1 already holds its coreness and can never be
+// activated: it gets no class (kClasses) and no list space.  Only classes 2
+// and 3 keep pruned lists.
 template <typename Off>
 __global__ __launch_bounds__(256) void k_init(Args<Off> a, int32_t r0, int32_t t0, int32_t t1, int32_t t2) {
   __shared__ uint32_t part[kClasses][256 / kWave];
@@ -1071,8 +1074,8 @@ __global__ __launch_bounds__(256) void k_init(Args<Off> a, int32_t r0, int32_t t
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
     const int32_t d = (int32_t)(a.row_ptr[v + 1] - a.row_ptr[v]);
     a.est[v] = d;
-    a.plen[v] = 0;
-    const uint8_t c = d <= t0 ? 0 : (d <= t1 ? 1 : (d <= t2 ? 2 : 3));
+    const uint8_t c = d <= 1 ? kClasses : (d <= t0 ? 0 : (d <= t1 ? 1 : (d <= t2 ? 2 : 3)));
+    if (c == 2 || c == 3) a.plen[v] = 0;
     a.cls[v] = c;
 #pragma unroll
     for (int k = 0; k < kClasses; ++k) p[k] += c == k;
@@ -1113,16 +1116,23 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
   const int64_t w0 = (int64_t)blockIdx.x * chunk + wave * wchunk, w1 = min(n, w0 + wchunk);
   // class of each vertex of a piece (kClasses: not in the list)
   auto piece = [&](int64_t pb, int32_t (&c)[P]) {
+    if (SEED) {  // every vertex with a class (degree >= 2)
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const int64_t v = pb + i * kWave + lane;
-      c[i] = v < w1 ? (SEED ? a.est[v] : a.stamp[v]) : -1;
+      for (int i = 0; i < P; ++i) {
+        const int64_t v = pb + i * kWave + lane;
+        c[i] = v < w1 ? (int32_t)a.cls[v] : kClasses;
+      }
+      return;
     }
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int64_t v = pb + i * kWave + lane;
-      const bool act = SEED ? c[i] >= 2 : c[i] == round;
-      c[i] = act ? (int32_t)a.cls[v] : kClasses;
+      c[i] = v < w1 ? a.stamp[v] : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int64_t v = pb + i * kWave + lane;
+      c[i] = c[i] == round ? (int32_t)a.cls[v] : kClasses;
     }
   };
   int32_t mine[kClasses] = {0, 0, 0, 0};

@@ -21,7 +21,7 @@ struct Tuning {
   int grid;       // workgroups per small-class round launch
   int big_grid;   // workgroups per class-3 round launch
   int poll;       // rounds in the first chunk between host checks
-  int one_sided;  // activation rule
+  int one_sided;  // activation rule: 1 one-sided, 0 two-sided, -1 chosen from the graph (settle_activation)
   int timing;     // HIP events around every round launch
   int list_cap;   // sparse list capacity per class
   int prune;      // pruned adjacency on/off
@@ -31,6 +31,8 @@ struct Tuning {
 };
 
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus);
+// Fixes an automatic activation rule for a graph (or batch) of n vertices and nnz entries.
+void settle_activation(Tuning* tu, int64_t n, int64_t nnz);
 kcore_status fail(kcore_status s, const std::string& msg);
 kcore_status hip_fail(hipError_t e, const char* what);
 

@@ -187,7 +187,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.grid = 8 * num_cus;
   r.big_grid = 4 * num_cus;
   r.poll = 4;
-  r.one_sided = 0;
+  r.one_sided = -1;
   r.timing = 0;
   r.list_cap = 8192;
   r.prune = 1;
@@ -204,7 +204,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
     if (t->grid_blocks > 0) r.grid = t->grid_blocks;
     if (t->big_grid_blocks > 0) r.big_grid = t->big_grid_blocks;
     if (t->rounds_per_poll > 0) r.poll = t->rounds_per_poll;
-    r.one_sided = t->activation == 1;
+    if (t->activation == 1 || t->activation == 2) r.one_sided = t->activation == 1;
     r.timing = t->timing == 1;
     if (t->list_cap > 0) r.list_cap = t->list_cap;
     r.prune = t->no_prune != 1;
@@ -221,6 +221,15 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.grid = std::max(8, (r.grid + 7) / 8 * 8);
   r.big_grid = std::max(1, r.big_grid);
   return r;
+}
+
+// On very sparse graphs (road networks: mean degree 2-3) a dropped estimate
+// rarely leaves a neighbour's support intact, so the two-sided filter saves few
+// recomputations and its slack atomics cost more than they save; there the
+// one-sided rule is faster.  Denser graphs gain from the filter.
+constexpr int64_t kOneSidedMeanDeg = 4;
+void settle_activation(Tuning* tu, int64_t n, int64_t nnz) {
+  if (tu->one_sided < 0) tu->one_sided = nnz < kOneSidedMeanDeg * n;
 }
 
 static bool env_flag(const char* name) {
@@ -632,7 +641,8 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
     s = validate_csr<Off>(ws, n, row_ptr, col, st);
     if (s != KCORE_OK) return s;
   }
-  const Tuning tu = resolve_tuning(tuning, ws->num_cus);
+  Tuning tu = resolve_tuning(tuning, ws->num_cus);
+  settle_activation(&tu, n, nnz);
   if (tu.relabel && n > 1 && n < INT32_MAX - 1 && nnz > 0) {
     int64_t long_rows = 0, long_entries = 0;
     s = relabel_probe<Off>(ws, n, row_ptr, &long_rows, &long_entries, st);
@@ -742,7 +752,8 @@ static kcore_status batch_impl(int32_t G, const int64_t* gvo, const int64_t* row
   kcore_tuning cached;
   const kcore_tuning* use = tuning;
   if (!use && tune_lookup(G, n, nnz, &cached)) use = &cached;
-  const Tuning tu = resolve_tuning(use, ws->num_cus);
+  Tuning tu = resolve_tuning(use, ws->num_cus);
+  settle_activation(&tu, n, nnz);
   return run_rounds<true, int64_t>(ws, n, nnz, row_ptr, col, out, tu, stats, st);
 }
 
@@ -792,6 +803,7 @@ static kcore_status autotune_impl(int32_t G, const int64_t* gvo, const int64_t* 
       {&kcore_tuning::group_max_deg, {32, 64}},
       {&kcore_tuning::wave_max_deg, {256, 512}},
       {&kcore_tuning::rounds_per_poll, {2, 4, 8}},
+      {&kcore_tuning::activation, {1, 2}},
   };
   for (const auto& k : knobs) {
     for (int32_t val : k.values) {
@@ -871,6 +883,7 @@ kcore_status serve_arena_create(ServeArena* A, int device, int64_t nv, int64_t n
   A->ne = std::max<int64_t>(ne, 1);
   A->max_slots = max_slots;
   A->tu = resolve_tuning(tuning, A->num_cus);
+  if (A->tu.one_sided < 0) A->tu.one_sided = 0;  // graphs of any density share the rounds
   size_t bytes = 0;
   auto alloc = [&](auto** p, size_t count) {
     const size_t b = sizeof(**p) * std::max<size_t>(count, 1);

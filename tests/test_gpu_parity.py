@@ -158,6 +158,8 @@ TUNINGS = {
     "no_tail": dict(tail_threshold=-1),
     "tail_everything": dict(tail_threshold=1 << 30),
     "one_sided": dict(activation=1),
+    "two_sided": dict(activation=2),
+    "two_sided_no_tail": dict(activation=2, tail_threshold=-1, list_cap=256),
     "tiny_grid": dict(grid_blocks=8, big_grid_blocks=1),
     "lane_only_small": dict(thread_max_deg=2, group_max_deg=16, wave_max_deg=64),
     "all_workgroup": dict(thread_max_deg=1, group_max_deg=1, wave_max_deg=1),
