@@ -68,6 +68,7 @@ constexpr int kBigBlock = 256;      // class 3: one workgroup per vertex
 constexpr int kBigRegs = 8;         // values per thread held in registers (2048 per workgroup)
 constexpr int kKary = 8;            // thresholds per pass of the k-ary search
 constexpr int kHistBins = 4096;     // LDS histogram bins of the one-pass search (16 KB)
+constexpr int kStash = 8192;        // LDS copies (16-bit) of the values read by the one-pass search (16 KB)
 constexpr int kCompactPerLane = 16; // vertices per lane read at once by the compaction kernel
 constexpr int kRelabelBuckets = 1024;  // degree buckets of the relabelling (larger degrees share the top one)
 constexpr int kRelabelLongDeg = 64;    // rows above this degree are copied by a wavefront when renumbering

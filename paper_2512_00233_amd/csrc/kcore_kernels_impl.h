@@ -650,9 +650,14 @@ __device__ __forceinline__ int32_t mp_search(const Args<Off>& a, const int32_t* 
 // with count(k) >= k, or lo - 1.  Values in [lo, top] (top = min(e, lo +
 // kHistBins - 1)) go to an LDS histogram, larger ones to one counter; if the
 // answer lies above top, the multi-pass search finishes over (top, e].
+// With `stash`, value j is also kept in LDS as min(x, e + 1), which keeps every
+// comparison the later passes make (x > h, x <= e, x >= L for L <= h <= e), so
+// that they need not gather the estimates again (the caller checks len <= kStash
+// and e + 1 < 2^16).
 template <int BLOCK, typename Off>
 __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t* src, int32_t off, int32_t len,
-                                               int32_t lo, int32_t e, int32_t* red, int32_t* hist, int32_t& count) {
+                                               int32_t lo, int32_t e, int32_t* red, int32_t* hist, int32_t& count,
+                                               uint16_t* stash) {
   constexpr int U = 8;  // loads in flight per thread
   const int tid = threadIdx.x;
   const int32_t top = (int32_t)min((int64_t)e, (int64_t)lo + kHistBins - 1);
@@ -669,6 +674,11 @@ __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) x[q] = c[q] >= 0 ? a.est[c[q]] : -1;
+    if (stash) {
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+        if (c[q] >= 0) stash[j0 + q * BLOCK + tid] = (uint16_t)min(x[q], e + 1);
+    }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       if (x[q] > top) above += 1;
@@ -719,7 +729,7 @@ __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t
 // histogram.  The pruned list is tried first.
 template <int BLOCK, bool BATCH, typename Off>
 __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32_t u, bool dense, int32_t round,
-                                        LaneStats& st, int32_t* red, int32_t* hist) {
+                                        LaneStats& st, int32_t* red, int32_t* hist, uint16_t* stash) {
   constexpr int R = kBigRegs;
   constexpr int CAPR = BLOCK * R;
   const int tid = threadIdx.x;
@@ -733,6 +743,9 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
   int32_t c[R], x[R];
   int32_t len = 0, soff = 0;
   bool inreg = false;
+  // the last one-pass search kept its values in LDS
+  bool stashed = false;
+  const bool stash_ok = e < 65535;
   const int32_t* src = a.col;
   auto load = [&](const int32_t* from, int32_t n_, int32_t off) {
     len = n_;
@@ -763,7 +776,8 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
       len = pl;
       src = a.pruned;
       soff = 0;
-      const int32_t hp = hist_search<BLOCK>(a, a.pruned + beg, 0, pl, L, e, red, hist, cnt);
+      stashed = stash_ok && pl <= kStash;
+      const int32_t hp = hist_search<BLOCK>(a, a.pruned + beg, 0, pl, L, e, red, hist, cnt, stashed ? stash : nullptr);
       if (hp >= L) h = hp;
     }
   }
@@ -798,7 +812,8 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
       len = d;
       src = a.col;
       soff = gb;
-      h = hist_search<BLOCK>(a, a.col + beg, gb, d, 1, e, red, hist, cnt);
+      stashed = stash_ok && d <= kStash;
+      h = hist_search<BLOCK>(a, a.col + beg, gb, d, 1, e, red, hist, cnt, stashed ? stash : nullptr);
       rebuild_pass = a.prune != 0;
     }
   }
@@ -829,7 +844,8 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
       v[q] = j < len ? soff + src[beg + j] : -1;
     }
 #pragma unroll
-    for (int q = 0; q < U; ++q) xv[q] = v[q] >= 0 ? a.est[v[q]] : 0;
+    for (int q = 0; q < U; ++q)
+      xv[q] = v[q] < 0 ? 0 : (stashed ? (int32_t)stash[j0 + q * BLOCK + tid] : a.est[v[q]]);
     if (rebuild_pass) {
       int32_t mine = 0;
 #pragma unroll
@@ -1228,6 +1244,7 @@ template <bool FIRST, bool BATCH, typename Off>
 __global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot, int32_t collect_stats) {
   constexpr int BLOCK = kBigBlock, NW = BLOCK / kWave;
   __shared__ int32_t hist[kHistBins];
+  __shared__ uint16_t stash[kStash];
   __shared__ int32_t red[kKary * NW];
   __shared__ unsigned long long red64[kLaneStats * NW];
   Ctl* ctl = a.ctl;
@@ -1239,7 +1256,7 @@ __global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot,
   const int nslot = (round + 1) % 3;
   const Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
   for (int32_t i = blockIdx.x; i < f.n[3]; i += gridDim.x)
-    upd_big<BLOCK, BATCH>(a, s, f.list[f.b[3] + i], FIRST, round, st, red, hist);
+    upd_big<BLOCK, BATCH>(a, s, f.list[f.b[3] + i], FIRST, round, st, red, hist, stash);
   if (collect_stats) flush_stats<BLOCK>(ctl, FIRST ? KI_BIG_FIRST : KI_BIG, st, red64);
 }
 
