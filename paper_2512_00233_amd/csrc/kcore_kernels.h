@@ -76,6 +76,7 @@ constexpr int kRelabelLongDeg = 64;    // rows above this degree are copied by a
 constexpr bool kBigFirst = true;
 constexpr int kPruneMarginNum = 1;  // pruned lists keep estimates >= h - h * num / den
 constexpr int kPruneMarginDen = 4;
+constexpr int kPruneCompactDen = 16;  // a class-3 pruned list is compacted once >= 1/16 of it is below L
 
 // Control block in device memory.  Counter slot s = round % 3.
 struct Ctl {

@@ -653,11 +653,11 @@ __device__ __forceinline__ int32_t mp_search(const Args<Off>& a, const int32_t* 
 // With `stash`, value j is also kept in LDS as min(x, e + 1), which keeps every
 // comparison the later passes make (x > h, x <= e, x >= L for L <= h <= e), so
 // that they need not gather the estimates again (the caller checks len <= kStash
-// and e + 1 < 2^16).
+// and e + 1 < 2^16).  `kept` receives the number of values >= lo.
 template <int BLOCK, typename Off>
 __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t* src, int32_t off, int32_t len,
                                                int32_t lo, int32_t e, int32_t* red, int32_t* hist, int32_t& count,
-                                               uint16_t* stash) {
+                                               uint16_t* stash, int32_t& kept) {
   constexpr int U = 8;  // loads in flight per thread
   const int tid = threadIdx.x;
   const int32_t top = (int32_t)min((int64_t)e, (int64_t)lo + kHistBins - 1);
@@ -693,6 +693,7 @@ __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t
   for (int32_t b = b0; b < b1; ++b) local += hist[b];
   int32_t total = 0;
   const int32_t before = block_excl_scan<BLOCK>(local, total, red);
+  kept = total + tot_above;
   int32_t run = tot_above + (total - before - local);  // values above my bins
   // candidate and its count, packed so that the maximum picks the largest candidate
   long long cand = -1;
@@ -726,7 +727,9 @@ __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t
 
 // One workgroup per vertex of class 3.  Lists of up to BLOCK * kBigRegs entries
 // are held in registers (k-ary search); longer ones use the one-pass LDS
-// histogram.  The pruned list is tried first.
+// histogram.  The pruned list is tried first.  When a search over it succeeds
+// and at least 1/kPruneCompactDen of its entries have fallen below its
+// threshold L (they can never rise again), the list is compacted in place.
 template <int BLOCK, bool BATCH, typename Off>
 __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32_t u, bool dense, int32_t round,
                                         LaneStats& st, int32_t* red, int32_t* hist, uint16_t* stash) {
@@ -764,21 +767,43 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
   };
   if (tid == 0) st.v[ST_UPDATES] += 1;
   int32_t h = -1, cnt = 0;
+  bool compact_pass = false;  // the streaming pass compacts the pruned list
   if (pl > 0) {
     if (tid == 0) st.v[ST_VISITS] += pl;
     if (pl <= CAPR) {
       load(a.pruned, pl, 0);
       inreg = true;
       const int32_t hp = kary_block<BLOCK, R>(x, e, L, red, cnt);
-      if (hp >= L) h = hp;
+      if (hp >= L) {
+        h = hp;
+        int32_t mine = 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) mine += (tid + BLOCK * i < pl) && x[i] >= L;
+        int32_t kept = 0;
+        int32_t off = block_excl_scan<BLOCK>(mine, kept, red);
+        if ((pl - kept) * kPruneCompactDen >= pl) {
+#pragma unroll
+          for (int i = 0; i < R; ++i)
+            if ((tid + BLOCK * i < pl) && x[i] >= L) a.pruned[beg + off++] = c[i];
+          if (tid == 0) {
+            a.plen[u] = kept;
+            st.v[ST_PRUNE_WRITES] += kept;
+          }
+        }
+      }
     } else {
       inreg = false;
       len = pl;
       src = a.pruned;
       soff = 0;
       stashed = stash_ok && pl <= kStash;
-      const int32_t hp = hist_search<BLOCK>(a, a.pruned + beg, 0, pl, L, e, red, hist, cnt, stashed ? stash : nullptr);
-      if (hp >= L) h = hp;
+      int32_t kept = 0;
+      const int32_t hp =
+          hist_search<BLOCK>(a, a.pruned + beg, 0, pl, L, e, red, hist, cnt, stashed ? stash : nullptr, kept);
+      if (hp >= L) {
+        h = hp;
+        compact_pass = (pl - kept) * kPruneCompactDen >= pl;
+      }
     }
   }
   bool rebuild_pass = false;
@@ -813,13 +838,14 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
       src = a.col;
       soff = gb;
       stashed = stash_ok && d <= kStash;
-      h = hist_search<BLOCK>(a, a.col + beg, gb, d, 1, e, red, hist, cnt, stashed ? stash : nullptr);
+      int32_t kept = 0;
+      h = hist_search<BLOCK>(a, a.col + beg, gb, d, 1, e, red, hist, cnt, stashed ? stash : nullptr, kept);
       rebuild_pass = a.prune != 0;
     }
   }
   if (tid == 0) a.slack[u] = cnt - h;
   const bool changed = h < e;
-  if (!changed && !rebuild_pass) return;
+  if (!changed && !rebuild_pass && !compact_pass) return;
   if (changed && tid == 0) {
     a.est[u] = h;
     st.v[ST_CHANGES] += 1;
@@ -832,9 +858,13 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
     return;
   }
   // streaming pass over the list, U entries per thread at a time: activation
-  // and/or rebuilding the pruned list (one workgroup scan per U * BLOCK entries)
+  // and/or writing the pruned list (one workgroup scan per U * BLOCK entries):
+  // a rebuild from the full list keeps values >= prune_low(h); the compaction of
+  // the pruned list in place keeps values >= L (a position is written only after
+  // the barrier that follows its read, and never ahead of the positions read)
   constexpr int U = 8;
-  const int32_t L2 = prune_low(h);
+  const bool write_pass = rebuild_pass || compact_pass;
+  const int32_t L2 = compact_pass ? L : prune_low(h);
   int32_t written = 0;
   for (int32_t j0 = 0; j0 < len; j0 += BLOCK * U) {
     int32_t v[U], xv[U];
@@ -846,7 +876,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
 #pragma unroll
     for (int q = 0; q < U; ++q)
       xv[q] = v[q] < 0 ? 0 : (stashed ? (int32_t)stash[j0 + q * BLOCK + tid] : a.est[v[q]]);
-    if (rebuild_pass) {
+    if (write_pass) {
       int32_t mine = 0;
 #pragma unroll
       for (int q = 0; q < U; ++q) mine += v[q] >= 0 && xv[q] >= L2;
@@ -867,7 +897,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
       activate_changed<U, true>(a, s, v, xv, in, e, h, dense, round, st, gb);
     }
   }
-  if (rebuild_pass && tid == 0) {
+  if (write_pass && tid == 0) {
     a.plen[u] = written;
     a.plow[u] = L2;
     st.v[ST_PRUNE_WRITES] += written;
@@ -1234,9 +1264,6 @@ __global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t slot, int3
   }
 }
 
-// One round, class 3 (degree above the wavefront class): one workgroup per
-// vertex.  Runs before k_round of the same round; a round handed to the tail
-// has no class-3 vertex, so this kernel then finds nothing to do.
 // One round, class 3 (degree above the wavefront class): one workgroup per
 // vertex.  Runs before k_round of the same round; a round handed to the tail
 // has no class-3 vertex, so this kernel then finds nothing to do.
