@@ -9,7 +9,9 @@ m / t with m the number of undirected edges (nnz / 2).
 Prints ONE JSON line.  Extra objects:
   roofline      the dominant round kernel: algorithmic bytes per launch over
                 its average launch duration (HIP events on the launch stream),
-                against the 8 TB/s HBM peak;
+                against the 8 TB/s HBM peak; beside it, the device's measured
+                random-gather rate over the same adjacency (kcore_probe_gather)
+                and the kernel's edge visits per second against it;
   cpu_baseline  the CPU oracle (definition-level peeling, one thread) timed on
                 this host on the same graph;
   also          the other plain workloads (road / ER small) measured the same
@@ -91,7 +93,7 @@ def run_workload(name, steps, warmup, torch, kc, gg, roofline_runs=3):
     ci = torch.from_numpy(g.col_idx).to(dev)
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-    per_kernel = {k: {"bytes": 0, "ms": 0.0, "launches": 0} for k in kc.KERNELS}
+    per_kernel = {k: {"bytes": 0, "ms": 0.0, "launches": 0, "visits": 0} for k in kc.KERNELS}
     st = kc.Stats()
     for _ in range(roofline_runs):
         st = kc.Stats()
@@ -100,6 +102,7 @@ def run_workload(name, steps, warmup, torch, kc, gg, roofline_runs=3):
             per_kernel[k]["bytes"] += kernel_bytes(st.kernel[i])
             per_kernel[k]["ms"] += st.kernel[i].ms
             per_kernel[k]["launches"] += st.kernel[i].launches
+            per_kernel[k]["visits"] += st.kernel[i].edge_visits
     for _ in range(warmup):
         kc.decompose(rp, ci, out=out)
     torch.cuda.synchronize()
@@ -113,12 +116,32 @@ def run_workload(name, steps, warmup, torch, kc, gg, roofline_runs=3):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - wall0) / steps * 1e3
     ms = t0.elapsed_time(t1) / steps
+    per_kernel["_gather_probe"] = gather_rate(torch, kc, ci, out, stream)
     return g, out.cpu().numpy(), st, ms, wall, per_kernel
+
+
+def gather_rate(torch, kc, ci, vals, stream, reps=5):
+    """Entries per second of one bare gather pass vals[col_idx[j]] over the whole adjacency
+    (kcore_probe_gather, HIP events on the launch stream); None for an empty graph."""
+    if ci.numel() == 0:
+        return None
+    s = torch.zeros(1, dtype=torch.int64, device=ci.device)
+    kc.probe_gather(ci, vals, s, stream=stream)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(reps):
+        kc.probe_gather(ci, vals, s, stream=stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return ci.numel() * reps / (t0.elapsed_time(t1) * 1e-3)
 
 
 def roofline_of(per_kernel, workload, kc, runs=ROOFLINE_RUNS):
     """Dominant kernel (largest summed duration): algorithmic bytes per launch over its
     average launch duration, against the HBM peak."""
+    probe = per_kernel.get("_gather_probe")
+    per_kernel = {n: v for n, v in per_kernel.items() if not n.startswith("_")}
     name = max(per_kernel, key=lambda k: per_kernel[k]["ms"])
     k = per_kernel[name]
     launches = max(k["launches"], 1)
@@ -135,6 +158,11 @@ def roofline_of(per_kernel, workload, kc, runs=ROOFLINE_RUNS):
         # counter bytes (L2 <-> memory fabric, scaled) over the same average launch duration
         out["traffic_gbs"] = round(traffic / avg_s / 1e9, 1)
         out["traffic_frac"] = round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+    if probe and k["ms"] > 0:
+        # the same kernel's adjacency entries per second against a bare gather pass over the graph
+        visits_rate = k["visits"] / (k["ms"] * 1e-3)
+        out["gather_ceiling"] = {"unit": "G entries/s", "probe": round(probe / 1e9, 2),
+                                 "kernel": round(visits_rate / 1e9, 2), "frac": round(visits_rate / probe, 3)}
     return out
 
 
@@ -401,7 +429,7 @@ def main():
     kernels = {kc.KERNEL_SYMBOLS[k]: {"ms_per_run": round(v["ms"] / runs, 4),
                                       "launches_per_run": v["launches"] // runs,
                                       "algorithmic_gb_per_run": round(v["bytes"] / runs / 1e9, 4)}
-               for k, v in per_kernel.items()}
+               for k, v in per_kernel.items() if not k.startswith("_")}
 
     result = {
         "metric": "GTEPS to coreness fixpoint (plain kernel, one graph resident in HBM)",
@@ -446,7 +474,8 @@ def main():
         g2, _, st2, ms2, _, pk2 = run_workload(name, args.steps, args.warmup, torch, kc, gg, 1)
         also.append({"workload": name, "value": round(g2.nnz / 2 / (ms2 * 1e-3) / 1e9, 3), "unit": "GTEPS",
                      "ms_per_step": round(ms2, 4), "rounds": st2.rounds, "tail_rounds": st2.tail_rounds,
-                     "roofline_frac": roofline_of(pk2, name, kc, 1)["frac"]})
+                     "roofline_frac": roofline_of(pk2, name, kc, 1)["frac"],
+                     "gather_ceiling_frac": roofline_of(pk2, name, kc, 1).get("gather_ceiling", {}).get("frac")})
     result["also"] = also
 
     if not args.no_cpu_baseline:

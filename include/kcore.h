@@ -321,6 +321,21 @@ kcore_status kcore_serve_stats(kcore_server* server, kcore_serve_report* out);
  * resource is freed. */
 kcore_status kcore_serve_destroy(kcore_server* server);
 
+/* ---- measurement ---------------------------------------------------------
+ * The bare access pattern of the neighbour scan, the method's hotspot (Sec. III,
+ * Optimizations): *out_sum = sum of vals[idx[j]] for 0 <= j < m, in one pass
+ * (coalesced reads of idx, one random 4-byte gather of vals per entry).  Timed
+ * on a graph's col_idx it gives the device's random-gather rate for that
+ * adjacency, the practical ceiling of the round kernels' edge visits.
+ *   idx[m]     device, int32, every value in [0, n) (not checked: out-of-range
+ *              values read outside vals)
+ *   vals[n]    device, int32
+ *   out_sum    device, one int64, overwritten
+ * Asynchronous on `stream`.  KCORE_E_INVALID for a negative size or a null
+ * pointer where one is needed. */
+kcore_status kcore_probe_gather(const int32_t* idx, int64_t m, const int32_t* vals, int64_t n, int64_t* out_sum,
+                                void* stream);
+
 /* Thread-local message for the last non-OK status returned on this thread. */
 const char* kcore_last_error(void);
 

@@ -224,6 +224,8 @@ def load():
     lib.kcore_serve_stats.argtypes = [vp, ctypes.POINTER(ServeReport)]
     lib.kcore_serve_destroy.restype = i32
     lib.kcore_serve_destroy.argtypes = [vp]
+    lib.kcore_probe_gather.restype = i32
+    lib.kcore_probe_gather.argtypes = [vp, i64, vp, i64, vp, vp]
     _lib = lib
     return lib
 
@@ -304,6 +306,20 @@ def decompose_rounds(row_ptr, col_idx, out=None, tuning: Tuning | None = None, m
                                       ctypes.byref(tuning) if tuning is not None else None, recs, max_records,
                                       ctypes.byref(got), _stream_handle(stream)))
     return out, [recs[i].as_dict() for i in range(got.value)]
+
+
+def probe_gather(idx, vals, out_sum, stream=None):
+    """Enqueue one pass of sum(vals[idx[j]]) into out_sum (int64 CUDA tensor of one element): the bare
+    gather pattern of the neighbour scan, for measuring the device's random-gather rate (asynchronous)."""
+    import torch
+    for t, name in ((idx, "idx"), (vals, "vals")):
+        if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous int32 CUDA tensor")
+    if not out_sum.is_cuda or out_sum.dtype != torch.int64 or out_sum.numel() != 1:
+        raise ValueError("out_sum must be an int64 CUDA tensor of one element")
+    m = idx.numel()
+    _check(load().kcore_probe_gather(idx.data_ptr() if m else None, m, vals.data_ptr() if vals.numel() else None,
+                                     vals.numel(), out_sum.data_ptr(), _stream_handle(stream)))
 
 
 def _check_batch(graph_vtx_off, row_ptr, col_idx):

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libkcore.so")
-SOURCES = ["csrc/kcore_runtime.hip", "csrc/kcore_serve.hip"]
+SOURCES = ["csrc/kcore_runtime.hip", "csrc/kcore_serve.hip", "csrc/kcore_probe.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # packed FP32 instructions stay off (no float arithmetic on this path anyway)

@@ -44,6 +44,8 @@ def test_version_and_error_without_gpu():
     # argument checks run before any device call
     assert lib.kcore_decompose(-5, None, None, None, None) == -1
     assert b"n must be" in lib.kcore_last_error()
+    assert lib.kcore_probe_gather(None, -1, None, 0, None, None) == -1
+    assert b"probe" in lib.kcore_last_error()
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
