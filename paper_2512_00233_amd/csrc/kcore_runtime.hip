@@ -185,7 +185,9 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.t2 = kWaveMaxDeg;
   r.tail = 2048;
   r.grid = 8 * num_cus;
-  r.big_grid = 4 * num_cus;
+  // class 3: four workgroups fit a compute unit at a time; launching four
+  // times more lets the hardware hand vertices to whichever unit frees up first
+  r.big_grid = 16 * num_cus;
   r.poll = 4;
   r.one_sided = -1;
   r.timing = 0;
@@ -797,7 +799,7 @@ static kcore_status autotune_impl(int32_t G, const int64_t* gvo, const int64_t* 
   };
   const std::vector<Knob> knobs = {
       {&kcore_tuning::grid_blocks, {4 * cus, 8 * cus, 16 * cus}},
-      {&kcore_tuning::big_grid_blocks, {2 * cus, 4 * cus, 8 * cus}},
+      {&kcore_tuning::big_grid_blocks, {4 * cus, 16 * cus, 32 * cus}},
       {&kcore_tuning::list_cap, {2048, 8192, 32768}},
       {&kcore_tuning::tail_threshold, {512, 2048, 8192}},
       {&kcore_tuning::group_max_deg, {32, 64}},
