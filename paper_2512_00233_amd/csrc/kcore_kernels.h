@@ -130,6 +130,7 @@ struct Args {
   int32_t* slack;      // support at the own level minus the level, from the last recomputation
   int32_t* gact;       // served graphs: per graph (indexed by its base vertex) the last round it has work for
   int32_t served;      // 1: the served arenas (compaction range from the control block)
+  int32_t wave_max_deg;  // largest degree of classes 0..2 (an estimate above it belongs to class 3)
 };
 
 // A served graph's place in the arenas.

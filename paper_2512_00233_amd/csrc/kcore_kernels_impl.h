@@ -105,15 +105,21 @@ template <int N, bool BIG, typename Off>
 __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink& s, int32_t (&v)[N],
                                                  const int32_t (&x)[N], const bool (&in)[N], int32_t e, int32_t h,
                                                  bool dense, int32_t round, LaneStats& st, int32_t gb) {
+  const bool always = a.one_sided || dense;
+  // Two-sided rule in the classes-0..2 kernel: a neighbour read above both e and
+  // the largest class-0..2 degree is a class-3 vertex (estimates never exceed
+  // degrees) that the current vertex never counted at its level; whether or not
+  // it is in this round's frontier (the class-3 kernel is the other one), it
+  // needs nothing, so its stamp is not even read.
+  const int32_t skip_above = (!BIG && !always) ? max(e, a.wave_max_deg) : INT32_MAX;
   bool cand[N];
   bool any = false;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    cand[i] = in[i] && x[i] > h;
+    cand[i] = in[i] && x[i] > h && x[i] <= skip_above;
     any |= cand[i];
   }
   if (!ballot(any)) return;
-  const bool always = a.one_sided || dense;
   const bool compact_next = s.overflow && *(volatile int32_t*)s.overflow;
   if (always && compact_next) {
     // every candidate is activated and the next round's lists come from the

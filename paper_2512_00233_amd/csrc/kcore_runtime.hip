@@ -377,6 +377,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   a.tail_threshold = tu.tail;
   a.list_cap = tu.list_cap;
   a.one_sided = tu.one_sided;
+  a.wave_max_deg = tu.t2;
   a.prune = tu.prune;
   const int32_t collect = (stats || rec) ? 1 : 0;
   const bool trace_env = env_flag("KCORE_TRACE");
@@ -857,6 +858,7 @@ static Args<int64_t> serve_args(const ServeArena* A) {
   a.tail_threshold = A->tu.tail;
   a.list_cap = A->tu.list_cap;
   a.one_sided = A->tu.one_sided;
+  a.wave_max_deg = A->tu.t2;
   a.prune = A->tu.prune;
   a.gact = A->gact;
   return a;
