@@ -106,12 +106,13 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
                                                  const int32_t (&x)[N], const bool (&in)[N], int32_t e, int32_t h,
                                                  bool dense, int32_t round, LaneStats& st, int32_t gb) {
   const bool always = a.one_sided || dense;
-  // Two-sided rule in the classes-0..2 kernel: a neighbour read above both e and
-  // the largest class-0..2 degree is a class-3 vertex (estimates never exceed
-  // degrees) that the current vertex never counted at its level; whether or not
-  // it is in this round's frontier (the class-3 kernel is the other one), it
-  // needs nothing, so its stamp is not even read.
-  const int32_t skip_above = (!BIG && !always) ? max(e, a.wave_max_deg) : INT32_MAX;
+  // In the classes-0..2 kernel, a neighbour read above both e and the largest
+  // class-0..2 degree is a class-3 vertex (estimates never exceed degrees).  It
+  // is not updated concurrently (the class-3 kernel is the other one), so x is
+  // its value for this round, and the current vertex was never counted at that
+  // level: the drop cannot matter to it, under either rule and in any round, so
+  // its stamp is not even read.
+  const int32_t skip_above = BIG ? INT32_MAX : max(e, a.wave_max_deg);
   bool cand[N];
   bool any = false;
 #pragma unroll

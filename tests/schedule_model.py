@@ -16,12 +16,17 @@ writes and atomics of all vertices of a round interleaved at random:
   charged against its slack when x <= e (the two-sided rule), activated when
   the slack goes negative;
 * class-3 vertices (degree above `big_deg`) run before the others in a round
-  (after them with big_first=False).
+  (after them with big_first=False);
+* in every round, a class-0..2 vertex skips a class-3 candidate read above its
+  own old value (it was never counted at that level, and the class-3 vertex
+  is not updated concurrently).
 
 `rule` selects deliberate mistakes, so that tests can show the model would
 notice them: "no_frontier_clause" drops the re-activation of same-kernel
 frontier vertices, "no_kernel_order" runs both classes interleaved while
-keeping the rule that relies on their order.
+keeping the rule that relies on their order, "skip_in_class3_kernel" applies
+the class-3 skip inside the class-3 kernel too, where such a candidate may be
+updated concurrently.
 """
 import random
 
@@ -64,6 +69,9 @@ def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_r
         if h == e:
             return
         for v, x in reads:
+            if (not cur_big or rule == "skip_in_class3_kernel") and big[v] and x > e:
+                yield
+                continue
             if x > h and stamp[v] < r + 1:
                 act = False
                 if first:

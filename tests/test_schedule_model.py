@@ -35,7 +35,7 @@ def test_model_reaches_the_coreness_under_random_schedules(big_first):
             assert got == ref, (n, adj, big_deg)
 
 
-@pytest.mark.parametrize("rule", ["no_frontier_clause", "no_kernel_order"])
+@pytest.mark.parametrize("rule", ["no_frontier_clause", "no_kernel_order", "skip_in_class3_kernel"])
 def test_model_catches_broken_rules(rule):
     rng = random.Random(7)
     wrong = 0
