@@ -111,8 +111,9 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
   // is not updated concurrently (the class-3 kernel is the other one), so x is
   // its value for this round, and the current vertex was never counted at that
   // level: the drop cannot matter to it, under either rule and in any round, so
-  // its stamp is not even read.
-  const int32_t skip_above = BIG ? INT32_MAX : max(e, a.wave_max_deg);
+  // its stamp is not even read.  In the first round every class-3 vertex is in
+  // the next frontier already (k_big), so any neighbour above the bound is skipped.
+  const int32_t skip_above = BIG ? INT32_MAX : (dense && kBigFirst ? a.wave_max_deg : max(e, a.wave_max_deg));
   bool cand[N];
   bool any = false;
 #pragma unroll
@@ -852,11 +853,15 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
   }
   if (tid == 0) a.slack[u] = cnt - h;
   const bool changed = h < e;
-  if (!changed && !rebuild_pass && !compact_pass) return;
   if (changed && tid == 0) {
     a.est[u] = h;
     st.v[ST_CHANGES] += 1;
   }
+  // In the first round the neighbours need no notice: the classes-0..2 ones are
+  // updated after this kernel and read the new value, and every class-3 vertex
+  // puts itself in the next frontier (k_big).
+  const bool notify = changed && !(dense && kBigFirst);
+  if (!notify && !rebuild_pass && !compact_pass) return;
   if (inreg) {
     bool in[R];
 #pragma unroll
@@ -894,7 +899,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
         if (v[q] >= 0 && xv[q] >= L2) a.pruned[beg + written + off++] = v[q];
       written += total;
     }
-    if (changed) {
+    if (notify) {
       bool in[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
@@ -1289,8 +1294,17 @@ __global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot,
   LaneStats st;
   const int nslot = (round + 1) % 3;
   const Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
-  for (int32_t i = blockIdx.x; i < f.n[3]; i += gridDim.x)
-    upd_big<BLOCK, BATCH>(a, s, f.list[f.b[3] + i], FIRST, round, st, red, hist, stash);
+  for (int32_t i = blockIdx.x; i < f.n[3]; i += gridDim.x) {
+    const int32_t u = f.list[f.b[3] + i];
+    upd_big<BLOCK, BATCH>(a, s, u, FIRST, round, st, red, hist, stash);
+    if (FIRST && kBigFirst) {
+      // every class-3 vertex is in the second round's frontier
+      int32_t self[1] = {u};
+      const int32_t one[1] = {1};
+      const bool lead[1] = {threadIdx.x == 0};
+      activate_changed<1, true>(a, s, self, one, lead, INT32_MAX, 0, true, round, st, BATCH ? uni(a.vbase[u]) : 0);
+    }
+  }
   if (collect_stats) flush_stats<BLOCK>(ctl, FIRST ? KI_BIG_FIRST : KI_BIG, st, red64);
 }
 

@@ -19,7 +19,10 @@ writes and atomics of all vertices of a round interleaved at random:
   (after them with big_first=False);
 * in every round, a class-0..2 vertex skips a class-3 candidate read above its
   own old value (it was never counted at that level, and the class-3 vertex
-  is not updated concurrently).
+  is not updated concurrently);
+* in the first round (class-3 kernel first), a class-3 vertex notifies no
+  neighbour and puts itself in the next frontier instead, and class-0..2
+  vertices skip every class-3 candidate.
 
 `rule` selects deliberate mistakes, so that tests can show the model would
 notice them: "no_frontier_clause" drops the re-activation of same-kernel
@@ -66,10 +69,13 @@ def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_r
             est[u] = h
         slack[u] = sum(1 for x in xs if x >= h) - h
         yield
+        if first and big_first and cur_big:
+            stamp[u] = r + 1
+            return
         if h == e:
             return
         for v, x in reads:
-            if (not cur_big or rule == "skip_in_class3_kernel") and big[v] and x > e:
+            if (not cur_big or rule == "skip_in_class3_kernel") and big[v] and (x > e or (first and big_first)):
                 yield
                 continue
             if x > h and stamp[v] < r + 1:
