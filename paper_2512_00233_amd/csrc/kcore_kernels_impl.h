@@ -498,7 +498,7 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t& total, in
 // kKary * (BLOCK / 64) ints.
 template <int BLOCK, int R>
 __device__ __forceinline__ int32_t kary_block(const int32_t (&x)[R], int32_t e, int32_t lo, int32_t* red,
-                                              int32_t& count) {
+                                              int32_t& count, int32_t* count_lo = nullptr) {
   constexpr int S = kKary;
   constexpr int NW = BLOCK / kWave;
   const int wave = threadIdx.x / kWave;
@@ -534,6 +534,7 @@ __device__ __forceinline__ int32_t kary_block(const int32_t (&x)[R], int32_t e, 
     }
     __syncthreads();
     if (first) {
+      if (count_lo) *count_lo = c[S - 1];  // the first pass tests lo itself
       int qs = -1;
 #pragma unroll
       for (int q = S - 1; q >= 0; --q)
@@ -781,15 +782,15 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
     if (pl <= CAPR) {
       load(a.pruned, pl, 0);
       inreg = true;
-      const int32_t hp = kary_block<BLOCK, R>(x, e, L, red, cnt);
+      int32_t kept = 0;  // entries still >= L
+      const int32_t hp = kary_block<BLOCK, R>(x, e, L, red, cnt, &kept);
       if (hp >= L) {
         h = hp;
-        int32_t mine = 0;
-#pragma unroll
-        for (int i = 0; i < R; ++i) mine += (tid + BLOCK * i < pl) && x[i] >= L;
-        int32_t kept = 0;
-        int32_t off = block_excl_scan<BLOCK>(mine, kept, red);
         if ((pl - kept) * kPruneCompactDen >= pl) {
+          int32_t mine = 0;
+#pragma unroll
+          for (int i = 0; i < R; ++i) mine += (tid + BLOCK * i < pl) && x[i] >= L;
+          int32_t off = block_excl_scan<BLOCK>(mine, kept, red);
 #pragma unroll
           for (int i = 0; i < R; ++i)
             if ((tid + BLOCK * i < pl) && x[i] >= L) a.pruned[beg + off++] = c[i];
