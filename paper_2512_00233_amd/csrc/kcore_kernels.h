@@ -31,9 +31,9 @@
 //    cap; past the cap the next round rebuilds its lists from the stamps in
 //    one compaction pass (one atomic per workgroup and class).
 //  * The h-index search over values held in registers is k-ary: the first
-//    pass tests e, e-1, e-3, e-7, ... at once (most recomputations stop there),
-//    later passes split the remaining interval evenly.  Long adjacency lists
-//    use a one-pass LDS histogram instead.
+//    pass tests e, e-1, e-3, ... and the lower bound at once (kKary thresholds;
+//    most recomputations stop there), later passes split the remaining interval
+//    evenly.  Long adjacency lists use a one-pass LDS histogram instead.
 //  * Pruned adjacency: after a full scan that yields h, a vertex of degree
 //    > 64 keeps the neighbours whose estimate is >= L = h - h/4.  Estimates only
 //    decrease, so the pruned-away neighbours stay below L forever, and a
@@ -66,7 +66,10 @@ constexpr int kWaveRegs = 8;        // class 2: 64 lanes x 8 values
 constexpr int kWaveMaxDeg = kWave * kWaveRegs;           // 512
 constexpr int kBigBlock = 256;      // class 3: one workgroup per vertex
 constexpr int kBigRegs = 8;         // values per thread held in registers (2048 per workgroup)
-constexpr int kKary = 8;            // thresholds per pass of the k-ary search
+// Thresholds per pass of the k-ary search.  Each costs R ballots per pass and
+// the number of passes falls like log_k of the interval, so few thresholds are
+// cheapest (measured on rmat24: 3 best, 2 and 4 within 0.3%, 8 3% slower, 16 15%).
+constexpr int kKary = 3;
 constexpr int kHistBins = 4096;     // LDS histogram bins of the one-pass search (16 KB)
 constexpr int kStash = 8192;        // LDS copies (16-bit) of the values read by the one-pass search (16 KB)
 constexpr int kCompactPerLane = 16; // vertices per lane read at once by the compaction kernel

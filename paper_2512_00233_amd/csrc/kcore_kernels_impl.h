@@ -209,8 +209,8 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
 // largest k in [lo, e] with |{values >= k}| >= k (and that count in `count`),
 // or lo - 1 when the count at lo is below lo (possible only when the caller
 // does not know count(lo) >= lo).
-// Pass 1 tests e, e-1, e-3, e-7, ..., lo; later passes cut the remaining
-// interval into kKary pieces.  Every lane of the wavefront must call this.
+// Pass 1 tests e, e-1, e-3, ... (kKary - 1 of them) and lo; later passes cut the
+// remaining interval into kKary pieces.  Every lane of the wavefront must call this.
 template <int G, int R>
 __device__ __forceinline__ int32_t kary_regs(const int32_t (&x)[R], int32_t e, int32_t lo, bool active,
                                              int32_t& count) {
