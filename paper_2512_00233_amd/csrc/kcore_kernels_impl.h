@@ -186,6 +186,7 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
     int32_t mine = 0;
 #pragma unroll
     for (int i = 0; i < N; ++i) mine += p[i] == k;
+    if (!ballot(mine != 0)) continue;  // no winner of this class in the wavefront
     const int32_t incl = wave_incl_scan(mine);
     const int32_t tot = __shfl(incl, kWave - 1);
     if (tot == 0) continue;
