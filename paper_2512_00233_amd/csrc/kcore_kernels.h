@@ -79,6 +79,9 @@ constexpr int kRelabelLongDeg = 64;    // rows above this degree are copied by a
 constexpr bool kBigFirst = true;
 constexpr int kPruneMarginNum = 1;  // pruned lists keep estimates >= h - h * num / den
 constexpr int kPruneMarginDen = 4;
+// Class-3 lists built in the first round, where estimates fall furthest, keep a
+// wider margin (fewer full rescans in the second round).
+constexpr int kPruneFirstMarginDen = 3;
 constexpr int kPruneCompactDen = 16;  // a class-3 pruned list is compacted once >= 1/16 of it is below L
 
 // Control block in device memory.  Counter slot s = round % 3.

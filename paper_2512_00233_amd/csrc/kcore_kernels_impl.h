@@ -346,6 +346,8 @@ __device__ __forceinline__ void upd_lane(const Args<Off>& a, const Sink& s, int3
 // Threshold of a pruned list built after a full scan that gave h: neighbours
 // whose estimate is at least this are kept.
 __device__ __forceinline__ int32_t prune_low(int32_t h) { return max(2, h - (h * kPruneMarginNum) / kPruneMarginDen); }
+// The same for class-3 lists built in the first round.
+__device__ __forceinline__ int32_t prune_low_first(int32_t h) { return max(2, h - h / kPruneFirstMarginDen); }
 
 // ------------------------------------------------------------------ class 1: 16-lane group per vertex
 template <bool BATCH, typename Off>
@@ -827,7 +829,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
       inreg = true;
       h = kary_block<BLOCK, R>(x, e, 1, red, cnt);
       if (a.prune) {
-        const int32_t L2 = prune_low(h);
+        const int32_t L2 = dense ? prune_low_first(h) : prune_low(h);
         int32_t mine = 0;
 #pragma unroll
         for (int i = 0; i < R; ++i) mine += (tid + BLOCK * i < len) && x[i] >= L2;
@@ -878,7 +880,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
   // the barrier that follows its read, and never ahead of the positions read)
   constexpr int U = 8;
   const bool write_pass = rebuild_pass || compact_pass;
-  const int32_t L2 = compact_pass ? L : prune_low(h);
+  const int32_t L2 = compact_pass ? L : (dense ? prune_low_first(h) : prune_low(h));
   int32_t written = 0;
   for (int32_t j0 = 0; j0 < len; j0 += BLOCK * U) {
     int32_t v[U], xv[U];
