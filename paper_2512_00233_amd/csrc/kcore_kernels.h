@@ -84,6 +84,18 @@ constexpr int kPruneMarginDen = 4;
 constexpr int kPruneFirstMarginDen = 3;
 constexpr int kPruneCompactDen = 16;  // a class-3 pruned list is compacted once >= 1/16 of it is below L
 
+// During a run the estimate array holds value << 2 | degree class (classes
+// 0..3; a vertex of degree <= 1 is stored as class 0, it is never activated),
+// so that the gather of a neighbour's estimate also tells which round kernel
+// updates it.  Values fit 29 bits: the initial estimate is min(degree, kEstMax),
+// still an upper bound of the coreness (a coreness above 2^29 would need more
+// than 2^58 adjacency entries).  The last kernel of a run strips the class.
+constexpr int kEstShift = 2;
+constexpr int32_t kEstMax = (1 << 29) - 1;
+__host__ __device__ inline int32_t est_enc(int32_t value, int32_t cls) { return (value << kEstShift) | (cls & 3); }
+__host__ __device__ inline int32_t est_val(int32_t raw) { return raw >> kEstShift; }
+__host__ __device__ inline int32_t est_cls(int32_t raw) { return raw & 3; }
+
 // Control block in device memory.  Counter slot s = round % 3.
 struct Ctl {
   int32_t cnt[3][kClasses];       // sparse list sizes per class (may exceed the cap: then overflow is set)
@@ -136,7 +148,6 @@ struct Args {
   int32_t* slack;      // support at the own level minus the level, from the last recomputation
   int32_t* gact;       // served graphs: per graph (indexed by its base vertex) the last round it has work for
   int32_t served;      // 1: the served arenas (compaction range from the control block)
-  int32_t wave_max_deg;  // largest degree of classes 0..2 (an estimate above it belongs to class 3)
 };
 
 // A served graph's place in the arenas.

@@ -104,21 +104,22 @@ __device__ __forceinline__ Sink make_sink(const Args<Off>& a, int32_t next_round
 template <int N, bool BIG, typename Off>
 __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink& s, int32_t (&v)[N],
                                                  const int32_t (&x)[N], const bool (&in)[N], int32_t e, int32_t h,
-                                                 bool dense, int32_t round, LaneStats& st, int32_t gb) {
+                                                 bool dense, int32_t round, LaneStats& st, int32_t gb, uint32_t cb) {
   const bool always = a.one_sided || dense;
-  // In the classes-0..2 kernel, a neighbour read above both e and the largest
-  // class-0..2 degree is a class-3 vertex (estimates never exceed degrees).  It
-  // is not updated concurrently (the class-3 kernel is the other one), so x is
-  // its value for this round, and the current vertex was never counted at that
-  // level: the drop cannot matter to it, under either rule and in any round, so
-  // its stamp is not even read.  In the first round every class-3 vertex is in
-  // the next frontier already (k_big), so any neighbour above the bound is skipped.
-  const int32_t skip_above = BIG ? INT32_MAX : (dense && kBigFirst ? a.wave_max_deg : max(e, a.wave_max_deg));
+  // cb holds each neighbour's class (2 bits each, from its estimate word).  A
+  // neighbour updated by the other kernel, read above e, needs nothing, under
+  // either rule and in any round: if that kernel runs later it reads the new
+  // value, otherwise x is already its value for the round (nothing updates it
+  // concurrently), and the current vertex was never counted at that level.  Its
+  // stamp is not even read.  In the first round every class-3 vertex is in the
+  // next frontier already (k_big), so the classes-0..2 kernel skips them all.
   bool cand[N];
   bool any = false;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    cand[i] = in[i] && x[i] > h && x[i] <= skip_above;
+    const bool other = (((cb >> (2 * i)) & 3u) == 3u) != BIG;
+    const bool skip = other && (x[i] > e || (!BIG && dense && kBigFirst));
+    cand[i] = in[i] && x[i] > h && !skip;
     any |= cand[i];
   }
   if (!ballot(any)) return;
@@ -139,9 +140,9 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
   int32_t sv[N], cv[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) sv[i] = cand[i] ? a.stamp[v[i]] : INT32_MAX;
-  // the class is needed for frontier members (which kernel updates them) and for winners
+  // the class tells frontier members' kernel and winners' list
 #pragma unroll
-  for (int i = 0; i < N; ++i) cv[i] = (!always && cand[i] && sv[i] == round) ? (int32_t)a.cls[v[i]] : -1;
+  for (int i = 0; i < N; ++i) cv[i] = (int32_t)((cb >> (2 * i)) & 3u);
   uint32_t want = 0, sub = 0;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -178,8 +179,7 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
   if (a.gact && first) a.gact[gb] = s.stamp;
   if (!ballot(first != 0)) return;
 #pragma unroll
-  for (int i = 0; i < N; ++i)
-    p[i] = (first >> i & 1u) ? (cv[i] >= 0 ? cv[i] : (int32_t)a.cls[v[i]]) : kClasses;  // class of winners
+  for (int i = 0; i < N; ++i) p[i] = (first >> i & 1u) ? cv[i] : kClasses;  // class of winners
   const int lane = lane_id();
 #pragma unroll
   for (int k = 0; k < kClasses; ++k) {
@@ -302,7 +302,7 @@ __device__ __forceinline__ void upd_lane(const Args<Off>& a, const Sink& s, int3
   if (valid) {
     beg = a.row_ptr[u];
     d = (int32_t)(a.row_ptr[u + 1] - beg);
-    e = a.est[u];
+    e = est_val(a.est[u]);
     if (BATCH) gb = a.vbase[u];
   }
   valid = valid && e >= 2;  // an estimate of 1 is final: every non-isolated vertex has coreness >= 1
@@ -311,6 +311,12 @@ __device__ __forceinline__ void upd_lane(const Args<Off>& a, const Sink& s, int3
   for (int i = 0; i < kLaneMaxDeg; ++i) c[i] = (valid && i < d) ? gb + a.col[beg + i] : 0;
 #pragma unroll
   for (int i = 0; i < kLaneMaxDeg; ++i) x[i] = (valid && i < d) ? a.est[c[i]] : 0;
+  uint32_t cb = 0;
+#pragma unroll
+  for (int i = 0; i < kLaneMaxDeg; ++i) {
+    cb |= (uint32_t)est_cls(x[i]) << (2 * i);
+    x[i] = est_val(x[i]);
+  }
   int32_t h = e;
   if (valid) {
     st.v[ST_UPDATES] += 1;
@@ -331,7 +337,7 @@ __device__ __forceinline__ void upd_lane(const Args<Off>& a, const Sink& s, int3
           break;
         }
       }
-      a.est[u] = h;
+      a.est[u] = est_enc(h, 0);
       st.v[ST_CHANGES] += 1;
     }
     a.slack[u] = cnt - h;
@@ -340,7 +346,7 @@ __device__ __forceinline__ void upd_lane(const Args<Off>& a, const Sink& s, int3
   bool in[kLaneMaxDeg];
 #pragma unroll
   for (int i = 0; i < kLaneMaxDeg; ++i) in[i] = changed && i < d;
-  activate_changed<kLaneMaxDeg, false>(a, s, c, x, in, e, h, dense, round, st, gb);
+  activate_changed<kLaneMaxDeg, false>(a, s, c, x, in, e, h, dense, round, st, gb, cb);
 }
 
 // Threshold of a pruned list built after a full scan that gave h: neighbours
@@ -360,7 +366,7 @@ __device__ __forceinline__ void upd_group(const Args<Off>& a, const Sink& s, int
   if (valid) {
     beg = a.row_ptr[u];
     d = (int32_t)(a.row_ptr[u + 1] - beg);
-    e = a.est[u];
+    e = est_val(a.est[u]);
     if (BATCH) gb = a.vbase[u];
   }
   valid = valid && e >= 2;
@@ -372,6 +378,12 @@ __device__ __forceinline__ void upd_group(const Args<Off>& a, const Sink& s, int
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) x[r] = (valid && gl + G * r < d) ? a.est[c[r]] : 0;
+  uint32_t cb = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    cb |= (uint32_t)est_cls(x[r]) << (2 * r);
+    x[r] = est_val(x[r]);
+  }
   if (valid && gl == 0) {
     st.v[ST_UPDATES] += 1;
     st.v[ST_VISITS] += (uint64_t)d;
@@ -380,14 +392,14 @@ __device__ __forceinline__ void upd_group(const Args<Off>& a, const Sink& s, int
   const int32_t h = kary_regs<G, R>(x, e, 1, valid, cnt);
   const bool changed = valid && h < e;
   if (changed && gl == 0) {
-    a.est[u] = h;
+    a.est[u] = est_enc(h, 1);
     st.v[ST_CHANGES] += 1;
   }
   if (valid && gl == 0) a.slack[u] = cnt - h;
   bool in[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) in[r] = changed && (gl + G * r < d);
-  activate_changed<R, false>(a, s, c, x, in, e, h, dense, round, st, gb);
+  activate_changed<R, false>(a, s, c, x, in, e, h, dense, round, st, gb, cb);
 }
 
 // ------------------------------------------------------------------ class 2: wavefront per vertex
@@ -399,12 +411,13 @@ __device__ __forceinline__ void upd_wave(const Args<Off>& a, const Sink& s, int3
   const int lane = lane_id();
   const Off beg = a.row_ptr[u];
   const int32_t d = uni((int32_t)(a.row_ptr[u + 1] - beg));
-  const int32_t e = uni(a.est[u]);
+  const int32_t e = uni(est_val(a.est[u]));
   if (e < 2) return;
   const int32_t gb = BATCH ? uni(a.vbase[u]) : 0;
   const int32_t pl = a.prune ? uni(a.plen[u]) : 0;
   const int32_t L = pl > 0 ? uni(a.plow[u]) : 1;
   int32_t c[R], x[R];
+  uint32_t cb = 0;  // neighbour classes, 2 bits each
   int32_t len = 0;
   auto load = [&](const int32_t* src, int32_t n_, int32_t off) {
     len = n_;
@@ -417,6 +430,12 @@ __device__ __forceinline__ void upd_wave(const Args<Off>& a, const Sink& s, int3
     for (int i = 0; i < R; ++i) {
       const int j = lane + kWave * i;
       x[i] = (kWave * i < n_ && j < n_) ? a.est[c[i]] : 0;
+    }
+    cb = 0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      cb |= (uint32_t)est_cls(x[i]) << (2 * i);
+      x[i] = est_val(x[i]);
     }
   };
   if (lane == 0) st.v[ST_UPDATES] += 1;
@@ -456,13 +475,13 @@ __device__ __forceinline__ void upd_wave(const Args<Off>& a, const Sink& s, int3
   if (lane == 0) a.slack[u] = cnt - h;
   if (h == e) return;
   if (lane == 0) {
-    a.est[u] = h;
+    a.est[u] = est_enc(h, 2);
     st.v[ST_CHANGES] += 1;
   }
   bool in[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) in[i] = lane + kWave * i < len;
-  activate_changed<R, false>(a, s, c, x, in, e, h, dense, round, st, gb);
+  activate_changed<R, false>(a, s, c, x, in, e, h, dense, round, st, gb, cb);
 }
 
 // ------------------------------------------------------------------ class 3: workgroup per vertex
@@ -611,7 +630,7 @@ __device__ __forceinline__ int32_t mp_search(const Args<Off>& a, const int32_t* 
       cnt[q] = 0;
     }
     for (int32_t j = tid; j < len; j += BLOCK) {
-      const int32_t xv = a.est[off + src[j]];
+      const int32_t xv = est_val(a.est[off + src[j]]);
 #pragma unroll
       for (int q = 0; q < S; ++q) cnt[q] += xv >= t[q];
     }
@@ -662,10 +681,11 @@ __device__ __forceinline__ int32_t mp_search(const Args<Off>& a, const int32_t* 
 // with count(k) >= k, or lo - 1.  Values in [lo, top] (top = min(e, lo +
 // kHistBins - 1)) go to an LDS histogram, larger ones to one counter; if the
 // answer lies above top, the multi-pass search finishes over (top, e].
-// With `stash`, value j is also kept in LDS as min(x, e + 1), which keeps every
-// comparison the later passes make (x > h, x <= e, x >= L for L <= h <= e), so
-// that they need not gather the estimates again (the caller checks len <= kStash
-// and e + 1 < 2^16).  `kept` receives the number of values >= lo.
+// With `stash`, value j is also kept in LDS as min(x, e + 1) with its class
+// (the estimate word's layout, 16 bits), which keeps every comparison the later
+// passes make (x > h, x <= e, x >= L for L <= h <= e), so that they need not
+// gather the estimates again (the caller checks len <= kStash and e + 1 < 2^14).
+// `kept` receives the number of values >= lo.
 template <int BLOCK, typename Off>
 __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t* src, int32_t off, int32_t len,
                                                int32_t lo, int32_t e, int32_t* red, int32_t* hist, int32_t& count,
@@ -689,8 +709,10 @@ __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t
     if (stash) {
 #pragma unroll
       for (int q = 0; q < U; ++q)
-        if (c[q] >= 0) stash[j0 + q * BLOCK + tid] = (uint16_t)min(x[q], e + 1);
+        if (c[q] >= 0) stash[j0 + q * BLOCK + tid] = (uint16_t)est_enc(min(est_val(x[q]), e + 1), est_cls(x[q]));
     }
+#pragma unroll
+    for (int q = 0; q < U; ++q) x[q] = c[q] >= 0 ? est_val(x[q]) : -1;
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       if (x[q] > top) above += 1;
@@ -750,17 +772,18 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
   const int tid = threadIdx.x;
   const Off beg = a.row_ptr[u];
   const int32_t d = uni((int32_t)(a.row_ptr[u + 1] - beg));
-  const int32_t e = uni(a.est[u]);
+  const int32_t e = uni(est_val(a.est[u]));
   if (e < 2) return;
   const int32_t gb = BATCH ? uni(a.vbase[u]) : 0;
   const int32_t pl = a.prune ? uni(a.plen[u]) : 0;
   const int32_t L = pl > 0 ? uni(a.plow[u]) : 1;
   int32_t c[R], x[R];
+  uint32_t cb = 0;  // register path: neighbour classes, 2 bits each
   int32_t len = 0, soff = 0;
   bool inreg = false;
   // the last one-pass search kept its values in LDS
   bool stashed = false;
-  const bool stash_ok = e < 65535;
+  const bool stash_ok = e < (1 << 14) - 1;
   const int32_t* src = a.col;
   auto load = [&](const int32_t* from, int32_t n_, int32_t off) {
     len = n_;
@@ -775,6 +798,12 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
     for (int i = 0; i < R; ++i) {
       const int j = tid + BLOCK * i;
       x[i] = (BLOCK * i < n_ && j < n_) ? a.est[c[i]] : 0;
+    }
+    cb = 0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      cb |= (uint32_t)est_cls(x[i]) << (2 * i);
+      x[i] = est_val(x[i]);
     }
   };
   if (tid == 0) st.v[ST_UPDATES] += 1;
@@ -858,7 +887,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
   if (tid == 0) a.slack[u] = cnt - h;
   const bool changed = h < e;
   if (changed && tid == 0) {
-    a.est[u] = h;
+    a.est[u] = est_enc(h, 3);
     st.v[ST_CHANGES] += 1;
   }
   // In the first round the neighbours need no notice: the classes-0..2 ones are
@@ -870,7 +899,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
     bool in[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) in[i] = tid + BLOCK * i < len;
-    activate_changed<R, true>(a, s, c, x, in, e, h, dense, round, st, gb);
+    activate_changed<R, true>(a, s, c, x, in, e, h, dense, round, st, gb, cb);
     return;
   }
   // streaming pass over the list, U entries per thread at a time: activation
@@ -892,6 +921,12 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
 #pragma unroll
     for (int q = 0; q < U; ++q)
       xv[q] = v[q] < 0 ? 0 : (stashed ? (int32_t)stash[j0 + q * BLOCK + tid] : a.est[v[q]]);
+    uint32_t qb = 0;  // classes, 2 bits each
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      qb |= (uint32_t)est_cls(xv[q]) << (2 * q);
+      xv[q] = est_val(xv[q]);
+    }
     if (write_pass) {
       int32_t mine = 0;
 #pragma unroll
@@ -910,7 +945,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
         in[q] = v[q] >= 0;
         v[q] = max(v[q], 0);
       }
-      activate_changed<U, true>(a, s, v, xv, in, e, h, dense, round, st, gb);
+      activate_changed<U, true>(a, s, v, xv, in, e, h, dense, round, st, gb, qb);
     }
   }
   if (write_pass && tid == 0) {
@@ -930,7 +965,7 @@ __device__ __forceinline__ void upd_big_lite(const Args<Off>& a, const Sink& s, 
   const int tid = threadIdx.x;
   const Off beg = a.row_ptr[u];
   const int32_t d = uni((int32_t)(a.row_ptr[u + 1] - beg));
-  const int32_t e = uni(a.est[u]);
+  const int32_t e = uni(est_val(a.est[u]));
   if (e < 2) return;
   const int32_t gb = BATCH ? uni(a.vbase[u]) : 0;
   const int32_t pl = a.prune ? uni(a.plen[u]) : 0;
@@ -961,18 +996,21 @@ __device__ __forceinline__ void upd_big_lite(const Args<Off>& a, const Sink& s, 
   if (tid == 0) a.slack[u] = cnt - h;
   if (h == e) return;
   if (tid == 0) {
-    a.est[u] = h;
+    a.est[u] = est_enc(h, 3);
     st.v[ST_CHANGES] += 1;
   }
   for (int32_t j0 = 0; j0 < len; j0 += BLOCK) {
     const int32_t j = j0 + tid;
     int32_t v[1] = {0}, xv[1] = {0};
+    uint32_t cb = 0;
     bool in[1] = {j < len};
     if (in[0]) {
       v[0] = off + src[j];
       xv[0] = a.est[v[0]];
+      cb = (uint32_t)est_cls(xv[0]);
+      xv[0] = est_val(xv[0]);
     }
-    activate_changed<1, true>(a, s, v, xv, in, e, h, false, round, st, gb);
+    activate_changed<1, true>(a, s, v, xv, in, e, h, false, round, st, gb, cb);
   }
 }
 
@@ -1097,6 +1135,12 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
 }
 
 // ------------------------------------------------------------------ kernels
+// The estimates of a finished run (or of a stopped one) without their class bits.
+__global__ void k_decode(int32_t* est, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) est[v] = est_val(est[v]);
+}
+
 // Zero the control block (a kernel rather than a memset, so that the sequence
 // can be captured in a graph).
 __global__ void k_zero_ctl(Ctl* ctl) {
@@ -1135,8 +1179,8 @@ __global__ __launch_bounds__(256) void k_init(Args<Off> a, int32_t r0, int32_t t
   uint32_t p[kClasses] = {0, 0, 0, 0};
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
     const int32_t d = (int32_t)(a.row_ptr[v + 1] - a.row_ptr[v]);
-    a.est[v] = d;
     const uint8_t c = d <= 1 ? kClasses : (d <= t0 ? 0 : (d <= t1 ? 1 : (d <= t2 ? 2 : 3)));
+    a.est[v] = est_enc(min(d, kEstMax), c);
     if (c == 2 || c == 3) a.plen[v] = 0;
     a.cls[v] = c;
 #pragma unroll
@@ -1306,7 +1350,8 @@ __global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot,
       int32_t self[1] = {u};
       const int32_t one[1] = {1};
       const bool lead[1] = {threadIdx.x == 0};
-      activate_changed<1, true>(a, s, self, one, lead, INT32_MAX, 0, true, round, st, BATCH ? uni(a.vbase[u]) : 0);
+      activate_changed<1, true>(a, s, self, one, lead, INT32_MAX, 0, true, round, st, BATCH ? uni(a.vbase[u]) : 0,
+                                3u);
     }
   }
   if (collect_stats) flush_stats<BLOCK>(ctl, FIRST ? KI_BIG_FIRST : KI_BIG, st, red64);
@@ -1424,9 +1469,10 @@ __global__ __launch_bounds__(256) void k_slot_init(Args<Off> a, const SlotDesc* 
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < sd.n; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t v = sd.vb + i;
     const int32_t d = (int32_t)(a.row_ptr[v + 1] - a.row_ptr[v]);
-    a.est[v] = d;
+    const uint8_t c = d <= t0 ? 0 : (d <= t1 ? 1 : (d <= t2 ? 2 : 3));
+    a.est[v] = est_enc(min(d, kEstMax), c);
     a.plen[v] = 0;
-    a.cls[v] = d <= t0 ? 0 : (d <= t1 ? 1 : (d <= t2 ? 2 : 3));
+    a.cls[v] = c;
     const_cast<int32_t*>(a.vbase)[v] = sd.vb;
     if (d >= 2) a.stamp[v] = r;
   }

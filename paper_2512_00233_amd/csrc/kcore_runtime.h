@@ -84,6 +84,9 @@ kcore_status serve_join(ServeArena* A, int32_t nslots, int64_t max_n, const int3
 // control block are copied to the pinned host buffers.
 kcore_status serve_step(ServeArena* A, int32_t rounds, int32_t nslots, int32_t* host_status, void* host_ctl,
                         void* stream);
+// Strip the class bits from the estimates of a finished graph (vertices vb .. vb+n-1) before they are
+// copied out.
+kcore_status serve_decode(ServeArena* A, int64_t vb, int64_t n, hipStream_t st);
 // Round base and error flag of a control block copied to the host.
 int32_t serve_ctl_rbase(const void* host_ctl);
 int32_t serve_ctl_error(const void* host_ctl);

@@ -377,7 +377,6 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   a.tail_threshold = tu.tail;
   a.list_cap = tu.list_cap;
   a.one_sided = tu.one_sided;
-  a.wave_max_deg = tu.t2;
   a.prune = tu.prune;
   const int32_t collect = (stats || rec) ? 1 : 0;
   const bool trace_env = env_flag("KCORE_TRACE");
@@ -483,6 +482,9 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     if ((int64_t)r - r0 > (int64_t)1 << 24) return fail(KCORE_E_HIP, "round limit exceeded");
     K = trace ? 1 : std::min(2 * K, 64);
   }
+  // the estimates carry their class during the run
+  hipLaunchKernelGGL(k_decode, dim3(init_grid), dim3(kBlock), 0, st, out, n);
+  KC_HIP(hipGetLastError());
   const Ctl& hc = *ws->host_ctl;
   if (hc.error) return fail(KCORE_E_HIP, "tail round cap reached (internal error)");
   ws->epoch = r + 4;  // the round base already counts the tail's rounds
@@ -858,7 +860,6 @@ static Args<int64_t> serve_args(const ServeArena* A) {
   a.tail_threshold = A->tu.tail;
   a.list_cap = A->tu.list_cap;
   a.one_sided = A->tu.one_sided;
-  a.wave_max_deg = A->tu.t2;
   a.prune = A->tu.prune;
   a.gact = A->gact;
   return a;
@@ -928,6 +929,14 @@ kcore_status serve_join(ServeArena* A, int32_t nslots, int64_t max_n, const int3
   }
   hipLaunchKernelGGL(k_serve_join, dim3(1), dim3(64), 0, st, static_cast<Ctl*>(A->ctl), pop[0], pop[1], pop[2],
                      pop[3], nhi);
+  KC_HIP(hipGetLastError());
+  return KCORE_OK;
+}
+
+kcore_status serve_decode(ServeArena* A, int64_t vb, int64_t n, hipStream_t st) {
+  if (n <= 0) return KCORE_OK;
+  const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)A->num_cus * 4);
+  hipLaunchKernelGGL(k_decode, dim3(grid), dim3(kBlock), 0, st, A->est + vb, n);
   KC_HIP(hipGetLastError());
   return KCORE_OK;
 }

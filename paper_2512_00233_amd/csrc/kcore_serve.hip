@@ -397,6 +397,7 @@ struct kcore_server {
       r->r_last = act;
       r->st = St::Retiring;
       KC_HIP_RET(hipStreamWaitEvent(down, step_ev, 0));
+      if ((s = serve_decode(&arena, r->vb, r->n, down)) != KCORE_OK) return s;
       if (r->n > 0)
         KC_HIP_RET(hipMemcpyAsync(r->out, arena.est + r->vb, sizeof(int32_t) * r->n, hipMemcpyDeviceToHost, down));
       KC_HIP_RET(hipEventRecord(r->ev, down));

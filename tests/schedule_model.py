@@ -17,9 +17,9 @@ writes and atomics of all vertices of a round interleaved at random:
   the slack goes negative;
 * class-3 vertices (degree above `big_deg`) run before the others in a round
   (after them with big_first=False);
-* in every round, a class-0..2 vertex skips a class-3 candidate read above its
-  own old value (it was never counted at that level, and the class-3 vertex
-  is not updated concurrently);
+* in every round, a candidate of the other kernel (class 3 seen from classes
+  0..2, or the reverse) read above the vertex's own old value is skipped: it
+  was never counted at that level, and it is not updated concurrently;
 * in the first round (class-3 kernel first), a class-3 vertex notifies no
   neighbour and puts itself in the next frontier instead, and class-0..2
   vertices skip every class-3 candidate.
@@ -75,7 +75,8 @@ def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_r
         if h == e:
             return
         for v, x in reads:
-            if (not cur_big or rule == "skip_in_class3_kernel") and big[v] and (x > e or (first and big_first)):
+            other = big[v] != cur_big
+            if ((other or (rule == "skip_in_class3_kernel" and cur_big)) and (x > e or (first and big_first and not cur_big))):
                 yield
                 continue
             if x > h and stamp[v] < r + 1:
