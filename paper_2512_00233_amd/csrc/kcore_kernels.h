@@ -23,7 +23,9 @@
 //    round may have read u's old value and is re-activated; class 3 and the
 //    small classes are separate kernels in a fixed order, so a neighbour of
 //    the other group either reads u's new value later or has a final value
-//    already (activate_changed).  One-sided mode is kept as an option.
+//    already (activate_changed); read above u's old level it needs nothing at
+//    all.  The neighbour's class comes with its estimate (two low bits of the
+//    estimate word during a run).  One-sided mode is kept as an option.
 //  * Frontier membership is a per-vertex round stamp (atomicMax dedup).  The
 //    frontier is processed as four lists by degree class (lane <= 8,
 //    16-lane group <= 64, wavefront <= 512, workgroup above).  Activations
