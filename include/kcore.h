@@ -74,7 +74,11 @@ typedef struct kcore_tuning {
                               lines; the renumbering itself costs about one sweep of random reads, so it pays
                               only on some graphs); 0 or 1: no renumbering.  Results come back in the caller's
                               numbering */
-  int32_t reserved[2];
+  int32_t deferred;        /* checks of frontier neighbours updated in the same kernel: 1 deferred to the end
+                              of the round and decided by their final level and slack, 2 re-activated at once;
+                              0: automatic (deferred for single graphs of at least 2^20 vertices under the
+                              two-sided rule, otherwise re-activated) */
+  int32_t reserved;
 } kcore_tuning;
 
 /* Round kernels, as indices into kcore_stats.kernel.  The first round (every

@@ -51,7 +51,8 @@ class Tuning(ctypes.Structure):
         ("no_graph", ctypes.c_int32),
         ("max_rounds", ctypes.c_int32),
         ("relabel", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("deferred", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

@@ -84,6 +84,7 @@ constexpr int kPruneMarginDen = 4;
 // Class-3 lists built in the first round, where estimates fall furthest, keep a
 // wider margin (fewer full rescans in the second round).
 constexpr int kPruneFirstMarginDen = 3;
+constexpr int kDeferRegions = 128;  // regions of the deferred-check buffer (spreads the append counters)
 constexpr int kPruneCompactDen = 16;  // a class-3 pruned list is compacted once >= 1/16 of it is below L
 
 // During a run the estimate array holds value << 2 | degree class (classes
@@ -114,6 +115,9 @@ struct Ctl {
   int32_t rbase;                  // round number of slot 0 of the next chunk of round launches
   int32_t tail_pending;           // rounds run by a tail since the last base advance (stamps up to rbase + this)
   int32_t nhi;                    // served graphs: vertex-id bound of the live slots (compaction range)
+  // deferred same-kernel checks appended in the current round, one counter per
+  // buffer region (a workgroup appends to region blockIdx.x % kDeferRegions)
+  int32_t dcnt[128];
 };
 enum Stat {
   ST_UPDATES = 0, ST_VISITS, ST_CHANGES, ST_ACTIVATIONS, ST_PRUNE_WRITES, ST_FULL_SCANS, ST_ROUNDS,
@@ -150,6 +154,11 @@ struct Args {
   int32_t* slack;      // support at the own level minus the level, from the last recomputation
   int32_t* gact;       // served graphs: per graph (indexed by its base vertex) the last round it has work for
   int32_t served;      // 1: the served arenas (compaction range from the control block)
+  // Deferred same-kernel checks: (v, e, h) triples of frontier neighbours that
+  // may have read a vertex's old value e before it dropped to h (nullptr: such
+  // neighbours are re-activated instead).
+  int32_t* defer;
+  int32_t defer_cap;   // triples
 };
 
 // A served graph's place in the arenas.

@@ -59,6 +59,9 @@ struct Sink {
   int32_t stamp;      // round number of the next frontier
   int32_t b[kClasses];
   int32_t cap[kClasses];
+  int32_t* dcnt;      // this workgroup's deferred-check counter (nullptr: re-activate instead)
+  int32_t dbase;      // first triple of its buffer region
+  int32_t dcap;       // triples in the region
 };
 
 template <typename Off>
@@ -69,6 +72,9 @@ __device__ __forceinline__ Sink make_sink(const Args<Off>& a, int32_t next_round
   s.cnt = cnt;
   s.overflow = overflow;
   s.stamp = next_round;
+  s.dcnt = nullptr;
+  s.dbase = 0;
+  s.dcap = 0;
   region_bases(a.ctl, s.b);
 #pragma unroll
   for (int k = 0; k < kClasses; ++k) s.cap[k] = capped ? min(a.ctl->pop[k], a.list_cap) : a.ctl->pop[k];
@@ -143,17 +149,46 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
   // the class tells frontier members' kernel and winners' list
 #pragma unroll
   for (int i = 0; i < N; ++i) cv[i] = (int32_t)((cb >> (2 * i)) & 3u);
-  uint32_t want = 0, sub = 0;
+  uint32_t want = 0, sub = 0, dfr = 0;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     if (!cand[i] || sv[i] >= s.stamp) continue;  // not a candidate, or already in the next frontier
-    bool w = false, d = false;
+    bool w = false, d = false, q = false;
     if (always) w = true;
-    else if (sv[i] == round && (cv[i] == 3) == BIG) w = true;
+    else if (sv[i] == round && (cv[i] == 3) == BIG) (s.dcnt ? q : w) = true;  // same kernel
     else if (sv[i] == round && BIG == kBigFirst) w = false;  // v's kernel runs after this one
     else if (x[i] <= e) d = true;
     want |= (w ? 1u : 0u) << i;
     sub |= (d ? 1u : 0u) << i;
+    dfr |= (q ? 1u : 0u) << i;
+  }
+  const int lane = lane_id();
+  // A neighbour updated in this same kernel may have read the old value e.  Its
+  // check is deferred until the kernel is over (k_defer): then its level is
+  // final, and the drop matters only if it crossed that level, which the
+  // neighbour's slack decides.  Past the buffer's capacity it is re-activated.
+  if (s.dcnt && ballot(dfr != 0)) {
+    const int32_t mine = __popc(dfr);
+    const int32_t incl = wave_incl_scan(mine);
+    const int32_t tot = __shfl(incl, kWave - 1);
+    int32_t base = 0;
+    if (lane == kWave - 1) base = atomicAdd(s.dcnt, tot);
+    base = __shfl(base, kWave - 1);
+    int32_t pos = base + incl - mine;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (dfr >> i & 1u) {
+        if (pos < s.dcap) {
+          int32_t* t = a.defer + 3 * ((int64_t)s.dbase + pos);
+          t[0] = v[i];
+          t[1] = e;
+          t[2] = h;
+        } else {
+          want |= 1u << i;
+        }
+        ++pos;
+      }
+    }
   }
   int32_t p[N];
 #pragma unroll
@@ -180,7 +215,6 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
   if (!ballot(first != 0)) return;
 #pragma unroll
   for (int i = 0; i < N; ++i) p[i] = (first >> i & 1u) ? cv[i] : kClasses;  // class of winners
-  const int lane = lane_id();
 #pragma unroll
   for (int k = 0; k < kClasses; ++k) {
     int32_t mine = 0;
@@ -1135,6 +1169,48 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
 }
 
 // ------------------------------------------------------------------ kernels
+// Deferred same-kernel checks of a round, after both update kernels: for each
+// (v, e, h) whose drop from e to h may have been read stale by v, v's level is
+// now final; the drop matters only if h < level <= e, and then it is charged
+// to v's slack like any other loss (v is activated when the slack goes
+// negative).  A charge for a drop that v had in fact seen only makes the rule
+// more conservative.
+template <typename Off>
+__global__ __launch_bounds__(256) void k_defer(Args<Off> a, int32_t slot) {
+  if (!a.defer) return;
+  Ctl* ctl = a.ctl;
+  const int32_t round = ctl->rbase + slot;
+  // workgroups share out the regions: region blockIdx.x % kDeferRegions, slice blockIdx.x / kDeferRegions
+  const int reg = blockIdx.x % kDeferRegions;
+  const int slices = max(1u, gridDim.x / kDeferRegions);
+  const int slice = blockIdx.x / kDeferRegions;
+  if (slice >= slices) return;
+  const int32_t rcap = a.defer_cap / kDeferRegions;
+  const int32_t n = min(ctl->dcnt[reg], rcap);
+  if (n == 0) return;
+  const int nslot = (round + 1) % 3;
+  const Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
+  LaneStats st;
+  const int32_t* base = a.defer + 3 * (int64_t)reg * rcap;
+  for (int32_t i0 = slice * blockDim.x; i0 < n; i0 += slices * blockDim.x) {
+    const int32_t i = i0 + threadIdx.x;
+    int32_t v[1] = {0};
+    const int32_t one[1] = {1};
+    bool act[1] = {false};
+    uint32_t c = 0;
+    if (i < n) {
+      v[0] = base[3 * i];
+      const int32_t e = base[3 * i + 1], h = base[3 * i + 2];
+      const int32_t raw = a.est[v[0]];
+      const int32_t lv = est_val(raw);
+      c = (uint32_t)est_cls(raw);
+      if (h < lv && lv <= e && a.stamp[v[0]] < s.stamp) act[0] = atomicSub(&a.slack[v[0]], 1) <= 0;
+    }
+    // activation as in the first round (unconditional for the lanes that set act)
+    activate_changed<1, true>(a, s, v, one, act, INT32_MAX, 0, true, round, st, 0, c);
+  }
+}
+
 // The estimates of a finished run (or of a stopped one) without their class bits.
 __global__ void k_decode(int32_t* est, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1214,6 +1290,8 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
   __shared__ int32_t bbase[kClasses];
   Ctl* ctl = a.ctl;
   const int32_t round = ctl->rbase + slot;
+  // this round's deferred checks start empty (the previous round's were consumed by its k_defer)
+  if (!SEED && blockIdx.x == 0 && threadIdx.x < kDeferRegions) ctl->dcnt[threadIdx.x] = 0;
   if (!SEED && ctl->overflow[round % 3][0] == 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int64_t n = a.served ? (int64_t)ctl->nhi : a.n;  // served graphs: the range of the live slots
@@ -1315,7 +1393,13 @@ __global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t slot, int3
     return;
   }
   const int nslot = (round + 1) % 3;
-  const Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
+  Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
+  if (!FIRST && a.defer) {
+    const int reg = blockIdx.x % kDeferRegions;
+    s.dcnt = &ctl->dcnt[reg];
+    s.dcap = a.defer_cap / kDeferRegions;
+    s.dbase = reg * s.dcap;
+  }
   sweep_small<BLOCK, BATCH>(a, s, f, FIRST, round, blockIdx.x, gridDim.x, st);
   if (collect_stats) flush_stats<BLOCK>(ctl, FIRST ? KI_ROUND_FIRST : KI_ROUND, st, red64);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1341,7 +1425,13 @@ __global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot,
   if (f.n[3] == 0) return;
   LaneStats st;
   const int nslot = (round + 1) % 3;
-  const Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
+  Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
+  if (!FIRST && a.defer) {
+    const int reg = blockIdx.x % kDeferRegions;
+    s.dcnt = &ctl->dcnt[reg];
+    s.dcap = a.defer_cap / kDeferRegions;
+    s.dbase = reg * s.dcap;
+  }
   for (int32_t i = blockIdx.x; i < f.n[3]; i += gridDim.x) {
     const int32_t u = f.list[f.b[3] + i];
     upd_big<BLOCK, BATCH>(a, s, u, FIRST, round, st, red, hist, stash);

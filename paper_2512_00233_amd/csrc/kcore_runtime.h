@@ -28,11 +28,13 @@ struct Tuning {
   int use_graph;  // capture chunks of round launches as hipGraphs
   int max_rounds; // > 0: stop after this many rounds (tail off)
   int relabel;    // 1: renumber by degree first (single-graph calls)
+  int defer;      // deferred same-kernel checks: 1 on, 0 off, -1 chosen from the graph (settle_activation)
 };
 
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus);
-// Fixes an automatic activation rule for a graph (or batch) of n vertices and nnz entries.
-void settle_activation(Tuning* tu, int64_t n, int64_t nnz);
+// Fixes an automatic activation rule and the automatic choice of deferred same-kernel checks for a
+// graph (or batch) of n vertices and nnz entries.
+void settle_activation(Tuning* tu, int64_t n, int64_t nnz, bool batch);
 kcore_status fail(kcore_status s, const std::string& msg);
 kcore_status hip_fail(hipError_t e, const char* what);
 

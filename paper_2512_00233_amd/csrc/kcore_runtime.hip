@@ -49,6 +49,8 @@ struct Workspace {
   int32_t* plow = nullptr;
   int32_t* vbase = nullptr;
   int32_t* slack = nullptr;
+  int32_t* defer = nullptr;  // deferred same-kernel checks, 3 ints each
+  int64_t defer_cap = 0;
   int32_t* pruned = nullptr;
   Ctl* ctl = nullptr;
   Ctl* host_ctl = nullptr;      // pinned
@@ -109,12 +111,13 @@ struct Workspace {
     drop_graphs();
     release_relabel();
     for (void* p : {(void*)stamp, (void*)cls, (void*)lists[0], (void*)lists[1], (void*)slist, (void*)plen,
-                    (void*)plow, (void*)vbase, (void*)slack, (void*)pruned})
+                    (void*)plow, (void*)vbase, (void*)slack, (void*)defer, (void*)pruned})
       (void)hipFree(p);
     stamp = nullptr;
     cls = nullptr;
     lists[0] = lists[1] = nullptr;
-    slist = plen = plow = vbase = slack = pruned = nullptr;
+    slist = plen = plow = vbase = slack = defer = pruned = nullptr;
+    defer_cap = 0;
     cap_n = 0;
     cap_nnz = 0;
   }
@@ -145,6 +148,12 @@ static kcore_status get_workspace(Workspace** out) {
   return KCORE_OK;
 }
 
+// Deferred same-kernel checks per round: a quarter of the vertices, at least 1M
+// (beyond it, such neighbours are simply re-activated).
+static int64_t defer_capacity(int64_t n) {
+  return std::min<int64_t>(std::max<int64_t>(n / 4, 1 << 20), INT32_MAX / 3);
+}
+
 static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, bool batched, hipStream_t st) {
   const bool need_vbase = batched && !ws->vbase;
   if (n <= ws->cap_n && nnz <= ws->cap_nnz && !need_vbase) return KCORE_OK;
@@ -161,6 +170,7 @@ static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, bool 
             hipMalloc(&ws->plen, sizeof(int32_t) * cap) == hipSuccess &&
             hipMalloc(&ws->plow, sizeof(int32_t) * cap) == hipSuccess &&
             hipMalloc(&ws->slack, sizeof(int32_t) * cap) == hipSuccess &&
+            hipMalloc(&ws->defer, sizeof(int32_t) * 3 * defer_capacity(cap)) == hipSuccess &&
             (!keep_vbase || hipMalloc(&ws->vbase, sizeof(int32_t) * cap) == hipSuccess) &&
 
             hipMalloc(&ws->pruned, sizeof(int32_t) * cap_e) == hipSuccess;
@@ -173,6 +183,7 @@ static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, bool 
   KC_HIP(hipMemsetAsync(ws->stamp, 0, sizeof(int32_t) * cap, st));
   ws->cap_n = cap;
   ws->cap_nnz = cap_e;
+  ws->defer_cap = defer_capacity(cap);
   ws->epoch = 1;
   return KCORE_OK;
 }
@@ -196,6 +207,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.use_graph = 1;
   r.max_rounds = 0;
   r.relabel = 0;
+  r.defer = -1;
   if (const char* e = std::getenv("KCORE_TAIL")) r.tail = std::atoi(e);
   if (t) {
     if (t->thread_max_deg > 0) r.t0 = std::min(t->thread_max_deg, kLaneMaxDeg);
@@ -212,6 +224,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
     r.prune = t->no_prune != 1;
     r.use_graph = t->no_graph != 1;
     r.relabel = t->relabel == 2;
+    if (t->deferred == 1 || t->deferred == 2) r.defer = t->deferred == 1;
     if (t->max_rounds > 0) {
       r.max_rounds = t->max_rounds;
       r.tail = 0;
@@ -230,8 +243,13 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
 // recomputations and its slack atomics cost more than they save; there the
 // one-sided rule is faster.  Denser graphs gain from the filter.
 constexpr int64_t kOneSidedMeanDeg = 4;
-void settle_activation(Tuning* tu, int64_t n, int64_t nnz) {
+// Deferred same-kernel checks remove most conservative re-activations, but cost
+// one more launch per round: measured, they pay on large single graphs and not
+// on small ones or on batches of many graphs.
+constexpr int64_t kDeferMinVertices = 1 << 20;
+void settle_activation(Tuning* tu, int64_t n, int64_t nnz, bool batch) {
   if (tu->one_sided < 0) tu->one_sided = nnz < kOneSidedMeanDeg * n;
+  if (tu->defer < 0) tu->defer = !batch && !tu->one_sided && n >= kDeferMinVertices;
 }
 
 static bool env_flag(const char* name) {
@@ -265,6 +283,10 @@ static void launch_updates(const Args<Off>& a, const Tuning& tu, int32_t slot, i
     hipLaunchKernelGGL((k_round<kBlock, FIRST, BATCH, Off>), dim3(tu.grid), dim3(kBlock), 0, st, a, slot, collect);
   else
     hipLaunchKernelGGL((k_big<FIRST, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, slot, collect);
+  // the deferred same-kernel checks of the round (none in the first round, nor under the one-sided
+  // rule, which re-activates every candidate)
+  if (!FIRST && a.defer && !a.one_sided)
+    hipLaunchKernelGGL((k_defer<Off>), dim3(4 * kDeferRegions), dim3(kBlock), 0, st, a, slot);
   if (ev) (void)hipEventRecord(ev[2], st);
 }
 
@@ -377,6 +399,8 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   a.tail_threshold = tu.tail;
   a.list_cap = tu.list_cap;
   a.one_sided = tu.one_sided;
+  a.defer = tu.defer > 0 ? ws->defer : nullptr;
+  a.defer_cap = (int32_t)ws->defer_cap;
   a.prune = tu.prune;
   const int32_t collect = (stats || rec) ? 1 : 0;
   const bool trace_env = env_flag("KCORE_TRACE");
@@ -647,7 +671,7 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
     if (s != KCORE_OK) return s;
   }
   Tuning tu = resolve_tuning(tuning, ws->num_cus);
-  settle_activation(&tu, n, nnz);
+  settle_activation(&tu, n, nnz, false);
   if (tu.relabel && n > 1 && n < INT32_MAX - 1 && nnz > 0) {
     int64_t long_rows = 0, long_entries = 0;
     s = relabel_probe<Off>(ws, n, row_ptr, &long_rows, &long_entries, st);
@@ -758,7 +782,7 @@ static kcore_status batch_impl(int32_t G, const int64_t* gvo, const int64_t* row
   const kcore_tuning* use = tuning;
   if (!use && tune_lookup(G, n, nnz, &cached)) use = &cached;
   Tuning tu = resolve_tuning(use, ws->num_cus);
-  settle_activation(&tu, n, nnz);
+  settle_activation(&tu, n, nnz, true);
   return run_rounds<true, int64_t>(ws, n, nnz, row_ptr, col, out, tu, stats, st);
 }
 
@@ -889,6 +913,7 @@ kcore_status serve_arena_create(ServeArena* A, int device, int64_t nv, int64_t n
   A->max_slots = max_slots;
   A->tu = resolve_tuning(tuning, A->num_cus);
   if (A->tu.one_sided < 0) A->tu.one_sided = 0;  // graphs of any density share the rounds
+  A->tu.defer = 0;                               // the arenas keep no deferred-check buffer
   size_t bytes = 0;
   auto alloc = [&](auto** p, size_t count) {
     const size_t b = sizeof(**p) * std::max<size_t>(count, 1);

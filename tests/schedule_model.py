@@ -11,10 +11,13 @@ writes and atomics of all vertices of a round interleaved at random:
   minus the value;
 * a change from e to h makes neighbour v (estimate x as read) a candidate when
   x > h; in the first round every candidate is activated (one-sided rule);
-  later, v is re-activated if it is updated in the same kernel of this round,
-  skipped if it is updated by the kernel that runs after the current one, and otherwise
-  charged against its slack when x <= e (the two-sided rule), activated when
-  the slack goes negative;
+  later, if v is updated in the same kernel of this round, the check is
+  deferred: once the round's kernels are over, the drop is charged to v's
+  slack if h < est(v) <= e, and v is activated when the slack goes negative
+  (with defer=False, v is re-activated at once instead); v is skipped if it is
+  updated by the kernel that runs after the current one, and otherwise charged
+  against its slack when x <= e (the two-sided rule), activated when the slack
+  goes negative;
 * class-3 vertices (degree above `big_deg`) run before the others in a round
   (after them with big_first=False);
 * in every round, a candidate of the other kernel (class 3 seen from classes
@@ -25,8 +28,9 @@ writes and atomics of all vertices of a round interleaved at random:
   vertices skip every class-3 candidate.
 
 `rule` selects deliberate mistakes, so that tests can show the model would
-notice them: "no_frontier_clause" drops the re-activation of same-kernel
-frontier vertices, "no_kernel_order" runs both classes interleaved while
+notice them: "no_frontier_clause" drops the re-activation (or the deferred
+check) of same-kernel frontier vertices, "defer_strict_level" defers the check
+but leaves out a level equal to e (a drop from e itself), "no_kernel_order" runs both classes interleaved while
 keeping the rule that relies on their order, "skip_in_class3_kernel" applies
 the class-3 skip inside the class-3 kernel too, where such a candidate may be
 updated concurrently.
@@ -44,7 +48,7 @@ def _hindex(vals, cap):
 
 
 def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_rounds: int = 10_000,
-              big_first: bool = True):
+              big_first: bool = True, defer: bool = True):
     """Coreness of the graph (adjacency lists) under one random schedule; returns (estimates, rounds)."""
     est = [len(adj[u]) for u in range(n)]
     big = [len(adj[u]) > big_deg for u in range(n)]
@@ -54,6 +58,7 @@ def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_r
     first = True
     frontier = [u for u in range(n) if est[u] >= 2]
     rounds = 0
+    deferred = []
 
     def proc(u, cur_big):
         e = est[u]
@@ -83,8 +88,13 @@ def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_r
                 act = False
                 if first:
                     act = True
-                elif stamp[v] == r and big[v] == cur_big and rule != "no_frontier_clause":
-                    act = True
+                elif stamp[v] == r and big[v] == cur_big:
+                    if rule == "no_frontier_clause":
+                        act = False
+                    elif defer:
+                        deferred.append((v, e, h))
+                    else:
+                        act = True
                 elif stamp[v] == r and cur_big == big_first:
                     act = False  # v is updated by the kernel that runs after the current one
                 elif x <= e:
@@ -109,6 +119,17 @@ def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_r
                     next(gens[i])
                 except StopIteration:
                     live.remove(i)
+        # the deferred same-kernel checks, after the round's kernels
+        rng.shuffle(deferred)
+        for v, e, h in deferred:
+            lv = est[v]
+            crossed = h < lv < e if rule == "defer_strict_level" else h < lv <= e
+            if crossed and stamp[v] < r + 1:
+                old = slack[v]
+                slack[v] = old - 1
+                if old <= 0:
+                    stamp[v] = r + 1
+        deferred.clear()
         first = False
         r += 1
         frontier = [u for u in range(n) if stamp[u] == r]

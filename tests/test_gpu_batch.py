@@ -73,7 +73,7 @@ def test_batch_edge_cases():
 
 @pytest.mark.parametrize("tuning", [dict(), dict(no_graph=1), dict(list_cap=1, tail_threshold=-1),
                                     dict(thread_max_deg=1, group_max_deg=1, wave_max_deg=1),
-                                    dict(activation=1, no_prune=1), dict(activation=2)])
+                                    dict(activation=1, no_prune=1), dict(activation=2), dict(deferred=1)])
 def test_batch_tunings(tuning):
     b = gg.batch(16, seed=5, nmin=1000, nmax=30_000)
     got = run_batch(b, tuning=kc().Tuning(**tuning))

@@ -158,6 +158,9 @@ TUNINGS = {
     "no_tail": dict(tail_threshold=-1),
     "tail_everything": dict(tail_threshold=1 << 30),
     "one_sided": dict(activation=1),
+    "deferred": dict(deferred=1),
+    "deferred_no_tail_small_cap": dict(deferred=1, tail_threshold=-1, list_cap=256),
+    "not_deferred": dict(deferred=2),
     "two_sided": dict(activation=2),
     "two_sided_no_tail": dict(activation=2, tail_threshold=-1, list_cap=256),
     "tiny_grid": dict(grid_blocks=8, big_grid_blocks=1),

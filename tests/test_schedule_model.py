@@ -26,16 +26,16 @@ def graphs(count, seed):
 CASES = graphs(1500, seed=11)
 
 
-@pytest.mark.parametrize("big_first", [True, False])
-def test_model_reaches_the_coreness_under_random_schedules(big_first):
+@pytest.mark.parametrize("big_first,defer", [(True, True), (False, True), (True, False)])
+def test_model_reaches_the_coreness_under_random_schedules(big_first, defer):
     rng = random.Random(5)
     for n, adj, ref in CASES:
         for big_deg in (rng.randint(1, 8), 1 << 30):
-            got, _ = run_model(n, adj, rng, big_deg, big_first=big_first)
+            got, _ = run_model(n, adj, rng, big_deg, big_first=big_first, defer=defer)
             assert got == ref, (n, adj, big_deg)
 
 
-@pytest.mark.parametrize("rule", ["no_frontier_clause", "no_kernel_order", "skip_in_class3_kernel"])
+@pytest.mark.parametrize("rule", ["no_frontier_clause", "no_kernel_order", "skip_in_class3_kernel", "defer_strict_level"])
 def test_model_catches_broken_rules(rule):
     rng = random.Random(7)
     wrong = 0
