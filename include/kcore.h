@@ -55,7 +55,8 @@ typedef struct kcore_tuning {
                               above: class 3, one workgroup per vertex */
   int32_t tail_threshold;  /* frontier work (lane = 1, group = 4, wavefront = 16) at or below which one
                               workgroup finishes the run (<0: never; default 2048) */
-  int32_t grid_blocks;     /* workgroups per small-class round launch (0: 8 per compute unit) */
+  int32_t grid_blocks;     /* workgroups per small-class round launch (0: 8 per compute unit, raised to one per
+                              32768 vertices, at most 32 per compute unit, for very large inputs) */
   int32_t big_grid_blocks; /* workgroups per class-3 round launch (0: 16 per compute unit) */
   int32_t rounds_per_poll; /* rounds enqueued before the first host check of the frontier */
   int32_t activation;      /* 0: automatic (one-sided when the mean degree is below 4, else two-sided; the

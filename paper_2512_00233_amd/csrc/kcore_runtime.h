@@ -19,6 +19,7 @@ struct Tuning {
   int t2;         // class 2 (wavefront): degree <= t2; above: class 3 (workgroup)
   int tail;       // frontier work that hands the run to one workgroup
   int grid;       // workgroups per small-class round launch
+  int grid_auto;  // 1: grid is the default, raised for very large inputs (settle_activation)
   int big_grid;   // workgroups per class-3 round launch
   int poll;       // rounds in the first chunk between host checks
   int one_sided;  // activation rule: 1 one-sided, 0 two-sided, -1 chosen from the graph (settle_activation)
