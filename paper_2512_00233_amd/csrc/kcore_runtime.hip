@@ -278,7 +278,7 @@ constexpr int kBlock = 256;
 // vertices per lane each, at most two per compute unit (few counter atomics).
 static int compact_grid(int64_t n, int num_cus) {
   const int64_t per_block = (int64_t)kBlock * kCompactPerLane * 4;
-  return (int)std::max<int64_t>(1, std::min<int64_t>((n + per_block - 1) / per_block, 2 * (int64_t)num_cus));
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + per_block - 1) / per_block, 8 * (int64_t)num_cus));
 }
 
 // The two update kernels of a round (slot relative to the round base), in
