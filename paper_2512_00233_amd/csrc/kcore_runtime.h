@@ -25,6 +25,7 @@ struct Tuning {
   int one_sided;  // activation rule: 1 one-sided, 0 two-sided, -1 chosen from the graph (settle_activation)
   int timing;     // HIP events around every round launch
   int list_cap;   // sparse list capacity per class
+  int list_cap_auto;  // 1: list_cap is the default, chosen per graph (settle_activation)
   int prune;      // pruned adjacency on/off
   int use_graph;  // capture chunks of round launches as hipGraphs
   int max_rounds; // > 0: stop after this many rounds (tail off)
