@@ -64,7 +64,7 @@ typedef struct kcore_tuning {
   int32_t timing;          /* 1: bracket every kernel launch with HIP events (fills the ms statistics) */
   int32_t list_cap;        /* frontier list capacity per degree class; beyond it the next round rebuilds
                               its lists from the round stamps (0: chosen per graph: 32768 for single graphs
-                              under the one-sided rule, 2048 for single graphs of at least 2^20 vertices under
+                              under the one-sided rule, 1024 for single graphs of at least 2^20 vertices under
                               the two-sided rule, otherwise 8192) */
   int32_t no_prune;        /* 1: disable the pruned adjacency (always scan the full neighbour list) */
   int32_t no_graph;        /* 1: launch every round directly instead of replaying captured hipGraphs */

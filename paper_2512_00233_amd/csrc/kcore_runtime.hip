@@ -272,11 +272,11 @@ void settle_activation(Tuning* tu, int64_t n, int64_t nnz, bool batch) {
   // graphs (one-sided rule) have thin frontiers, where appends beat a scan of
   // every stamp; large dense graphs see many repeated activations, which plain
   // stores and a compaction absorb best.  Measured: road 1.78 ms at 8192, 1.59
-  // ms at 32768; rmat24 27.8 ms at 8192, 26.5 ms at 2048; ER small (10,000
-  // vertices) best at 8192.
+  // ms at 32768, 1.69 ms at 65536; rmat24 27.8 ms at 8192, 26.2 ms at 2048,
+  // 26.0 ms at 1024, 26.2 ms at 512; ER small (10,000 vertices) best at 8192.
   if (tu->list_cap_auto && !batch) {
     if (tu->one_sided) tu->list_cap = 32768;
-    else if (n >= kDeferMinVertices) tu->list_cap = 2048;
+    else if (n >= kDeferMinVertices) tu->list_cap = 1024;
   }
 }
 
