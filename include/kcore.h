@@ -54,7 +54,8 @@ typedef struct kcore_tuning {
   int32_t wave_max_deg;    /* class 2, one wavefront per vertex: degree <= this (<= 512, default 512);
                               above: class 3, one workgroup per vertex */
   int32_t tail_threshold;  /* frontier work (lane = 1, group = 4, wavefront = 16) at or below which one
-                              workgroup finishes the run (<0: never; default 2048) */
+                              workgroup finishes the run (<0: never; 0: 512 for single graphs,
+                              2048 for the batched form) */
   int32_t grid_blocks;     /* workgroups per small-class round launch (0: 8 per compute unit, raised to one per
                               32768 vertices, at most 32 per compute unit, for very large inputs) */
   int32_t big_grid_blocks; /* workgroups per class-3 round launch (0: 16 per compute unit) */

@@ -26,6 +26,7 @@ struct Tuning {
   int timing;     // HIP events around every round launch
   int list_cap;   // sparse list capacity per class
   int list_cap_auto;  // 1: list_cap is the default, chosen per graph (settle_activation)
+  int tail_auto;      // 1: tail is the default, chosen per graph (settle_activation)
   int prune;      // pruned adjacency on/off
   int use_graph;  // capture chunks of round launches as hipGraphs
   int max_rounds; // > 0: stop after this many rounds (tail off)

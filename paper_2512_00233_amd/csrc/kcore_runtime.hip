@@ -195,6 +195,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.t1 = kGroupMaxDeg;
   r.t2 = kWaveMaxDeg;
   r.tail = 2048;
+  r.tail_auto = 1;
   r.grid = 8 * num_cus;
   r.grid_auto = 1;
   // class 3: four workgroups fit a compute unit at a time; launching four
@@ -210,13 +211,17 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.max_rounds = 0;
   r.relabel = 0;
   r.defer = -1;
-  if (const char* e = std::getenv("KCORE_TAIL")) r.tail = std::atoi(e);
+  if (const char* e = std::getenv("KCORE_TAIL")) {
+    r.tail = std::atoi(e);
+    r.tail_auto = 0;
+  }
   if (t) {
     if (t->thread_max_deg > 0) r.t0 = std::min(t->thread_max_deg, kLaneMaxDeg);
     if (t->group_max_deg > 0) r.t1 = std::min(t->group_max_deg, kGroupMaxDeg);
     if (t->wave_max_deg > 0) r.t2 = std::min(t->wave_max_deg, kWaveMaxDeg);
     if (t->tail_threshold > 0) r.tail = t->tail_threshold;
     else if (t->tail_threshold < 0) r.tail = 0;  // tail disabled
+    if (t->tail_threshold != 0) r.tail_auto = 0;
     if (t->grid_blocks > 0) {
       r.grid = t->grid_blocks;
       r.grid_auto = 0;
@@ -236,6 +241,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
     if (t->max_rounds > 0) {
       r.max_rounds = t->max_rounds;
       r.tail = 0;
+      r.tail_auto = 0;
     }
   }
   r.t0 = std::max(r.t0, 1);
@@ -278,6 +284,11 @@ void settle_activation(Tuning* tu, int64_t n, int64_t nnz, bool batch) {
     if (tu->one_sided) tu->list_cap = 32768;
     else if (n >= kDeferMinVertices) tu->list_cap = 1024;
   }
+  // Single graphs hand over to the one-workgroup tail later (road 1.59 ms at
+  // 2048, 1.56 ms at 512; rmat24 never reaches it; ER small unchanged).  The
+  // batched and served forms keep 2048 (the 2048-graph batch measured the same
+  // at 512).
+  if (tu->tail_auto && !batch) tu->tail = 512;
 }
 
 static bool env_flag(const char* name) {
