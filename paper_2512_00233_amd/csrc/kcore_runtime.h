@@ -19,25 +19,25 @@ struct Tuning {
   int t2;         // class 2 (wavefront): degree <= t2; above: class 3 (workgroup)
   int tail;       // frontier work that hands the run to one workgroup
   int grid;       // workgroups per small-class round launch
-  int grid_auto;  // 1: grid is the default, raised for very large inputs (settle_activation)
+  int grid_auto;  // 1: grid is the default, raised for very large inputs (settle_tuning)
   int big_grid;   // workgroups per class-3 round launch
   int poll;       // rounds in the first chunk between host checks
-  int one_sided;  // activation rule: 1 one-sided, 0 two-sided, -1 chosen from the graph (settle_activation)
+  int one_sided;  // activation rule: 1 one-sided, 0 two-sided, -1 chosen from the graph (settle_tuning)
   int timing;     // HIP events around every round launch
   int list_cap;   // sparse list capacity per class
-  int list_cap_auto;  // 1: list_cap is the default, chosen per graph (settle_activation)
-  int tail_auto;      // 1: tail is the default, chosen per graph (settle_activation)
+  int list_cap_auto;  // 1: list_cap is the default, chosen per graph (settle_tuning)
+  int tail_auto;      // 1: tail is the default, chosen per graph (settle_tuning)
   int prune;      // pruned adjacency on/off
   int use_graph;  // capture chunks of round launches as hipGraphs
   int max_rounds; // > 0: stop after this many rounds (tail off)
   int relabel;    // 1: renumber by degree first (single-graph calls)
-  int defer;      // deferred same-kernel checks: 1 on, 0 off, -1 chosen from the graph (settle_activation)
+  int defer;      // deferred same-kernel checks: 1 on, 0 off, -1 chosen from the graph (settle_tuning)
 };
 
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus);
-// Fixes an automatic activation rule and the automatic choice of deferred same-kernel checks for a
-// graph (or batch) of n vertices and nnz entries.
-void settle_activation(Tuning* tu, int64_t n, int64_t nnz, bool batch);
+// Fixes the defaults that depend on the input (small-class grid, activation rule, deferred
+// same-kernel checks, list cap, tail threshold) for a graph (or batch) of n vertices and nnz entries.
+void settle_tuning(Tuning* tu, int64_t n, int64_t nnz, bool batch);
 kcore_status fail(kcore_status s, const std::string& msg);
 kcore_status hip_fail(hipError_t e, const char* what);
 

@@ -266,7 +266,10 @@ constexpr int64_t kDeferMinVertices = 1 << 20;
 // vertices) runs 6% faster with 32 per unit, graphs of 16.8M vertices gain
 // nothing from it.
 constexpr int64_t kVerticesPerSmallBlock = 1 << 15;
-void settle_activation(Tuning* tu, int64_t n, int64_t nnz, bool batch) {
+// The defaults that depend on the input (n vertices, nnz adjacency entries; a
+// batch is many graphs sharing the rounds): small-class grid, activation rule,
+// deferred checks, list cap and tail threshold.  Knobs the caller set are kept.
+void settle_tuning(Tuning* tu, int64_t n, int64_t nnz, bool batch) {
   if (tu->grid_auto) {
     const int64_t want = (n + kVerticesPerSmallBlock - 1) / kVerticesPerSmallBlock;
     tu->grid = (int)std::min<int64_t>(std::max<int64_t>(want, tu->grid), 4 * (int64_t)tu->grid);
@@ -711,7 +714,7 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
     if (s != KCORE_OK) return s;
   }
   Tuning tu = resolve_tuning(tuning, ws->num_cus);
-  settle_activation(&tu, n, nnz, false);
+  settle_tuning(&tu, n, nnz, false);
   if (tu.relabel && n > 1 && n < INT32_MAX - 1 && nnz > 0) {
     int64_t long_rows = 0, long_entries = 0;
     s = relabel_probe<Off>(ws, n, row_ptr, &long_rows, &long_entries, st);
@@ -822,7 +825,7 @@ static kcore_status batch_impl(int32_t G, const int64_t* gvo, const int64_t* row
   const kcore_tuning* use = tuning;
   if (!use && tune_lookup(G, n, nnz, &cached)) use = &cached;
   Tuning tu = resolve_tuning(use, ws->num_cus);
-  settle_activation(&tu, n, nnz, true);
+  settle_tuning(&tu, n, nnz, true);
   return run_rounds<true, int64_t>(ws, n, nnz, row_ptr, col, out, tu, stats, st);
 }
 
