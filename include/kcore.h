@@ -58,7 +58,8 @@ typedef struct kcore_tuning {
                               2048 for the batched form) */
   int32_t grid_blocks;     /* workgroups per small-class round launch (0: 8 per compute unit, raised to one per
                               32768 vertices, at most 32 per compute unit, for very large inputs) */
-  int32_t big_grid_blocks; /* workgroups per class-3 round launch (0: 16 per compute unit) */
+  int32_t big_grid_blocks; /* workgroups per class-3 round launch (0: 16 per compute unit, 32 for
+                              single graphs of at least 2^20 vertices under the two-sided rule) */
   int32_t rounds_per_poll; /* rounds enqueued before the first host check of the frontier */
   int32_t activation;      /* 0: automatic (one-sided when the mean degree is below 4, else two-sided; the
                               served form always uses two-sided), 1: one-sided rule, 2: two-sided rule */

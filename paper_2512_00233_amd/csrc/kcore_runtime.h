@@ -26,6 +26,7 @@ struct Tuning {
   int timing;     // HIP events around every round launch
   int list_cap;   // sparse list capacity per class
   int list_cap_auto;  // 1: list_cap is the default, chosen per graph (settle_tuning)
+  int big_grid_auto;  // 1: big_grid is the default, chosen per graph (settle_tuning)
   int tail_auto;      // 1: tail is the default, chosen per graph (settle_tuning)
   int prune;      // pruned adjacency on/off
   int use_graph;  // capture chunks of round launches as hipGraphs
@@ -36,7 +37,7 @@ struct Tuning {
 
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus);
 // Fixes the defaults that depend on the input (small-class grid, activation rule, deferred
-// same-kernel checks, list cap, tail threshold) for a graph (or batch) of n vertices and nnz entries.
+// same-kernel checks, list cap, class-3 grid, tail threshold) for a graph (or batch) of n vertices and nnz entries.
 void settle_tuning(Tuning* tu, int64_t n, int64_t nnz, bool batch);
 kcore_status fail(kcore_status s, const std::string& msg);
 kcore_status hip_fail(hipError_t e, const char* what);

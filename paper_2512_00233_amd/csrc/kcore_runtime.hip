@@ -201,6 +201,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   // class 3: four workgroups fit a compute unit at a time; launching four
   // times more lets the hardware hand vertices to whichever unit frees up first
   r.big_grid = 16 * num_cus;
+  r.big_grid_auto = 1;
   r.poll = 4;
   r.one_sided = -1;
   r.timing = 0;
@@ -226,7 +227,10 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
       r.grid = t->grid_blocks;
       r.grid_auto = 0;
     }
-    if (t->big_grid_blocks > 0) r.big_grid = t->big_grid_blocks;
+    if (t->big_grid_blocks > 0) {
+      r.big_grid = t->big_grid_blocks;
+      r.big_grid_auto = 0;
+    }
     if (t->rounds_per_poll > 0) r.poll = t->rounds_per_poll;
     if (t->activation == 1 || t->activation == 2) r.one_sided = t->activation == 1;
     r.timing = t->timing == 1;
@@ -268,7 +272,7 @@ constexpr int64_t kDeferMinVertices = 1 << 20;
 constexpr int64_t kVerticesPerSmallBlock = 1 << 15;
 // The defaults that depend on the input (n vertices, nnz adjacency entries; a
 // batch is many graphs sharing the rounds): small-class grid, activation rule,
-// deferred checks, list cap and tail threshold.  Knobs the caller set are kept.
+// deferred checks, list cap, class-3 grid and tail threshold.  Knobs the caller set are kept.
 void settle_tuning(Tuning* tu, int64_t n, int64_t nnz, bool batch) {
   if (tu->grid_auto) {
     const int64_t want = (n + kVerticesPerSmallBlock - 1) / kVerticesPerSmallBlock;
@@ -287,6 +291,10 @@ void settle_tuning(Tuning* tu, int64_t n, int64_t nnz, bool batch) {
     if (tu->one_sided) tu->list_cap = 32768;
     else if (n >= kDeferMinVertices) tu->list_cap = 1024;
   }
+  // Class-3 workgroups: twice as many for large single graphs under the
+  // two-sided rule (rmat24 25.9 ms against 26.2 ms); road, ER small and the
+  // 2048-graph batch measured the same or slower.
+  if (tu->big_grid_auto && !batch && !tu->one_sided && n >= kDeferMinVertices) tu->big_grid *= 2;
   // Single graphs hand over to the one-workgroup tail later (road 1.59 ms at
   // 2048, 1.56 ms at 512; rmat24 never reaches it; ER small unchanged).  The
   // batched and served forms keep 2048 (the 2048-graph batch measured the same
