@@ -44,11 +44,12 @@ def algorithmic_bytes(updates, visits, changes, acts, off_bytes=8):
     return (2 * off_bytes + 8) * updates + 8 * visits + 4 * changes + 9 * acts
 
 
-KERNEL_SOURCES = ("kcore_kernels.h", "kcore_kernels_impl.h")
+KERNEL_SOURCES = ("kcore_kernels.h", "kcore_kernels_impl.h", "kcore_runtime.h", "kcore_runtime.hip")
 
 
 def kernel_source_hash():
-    """Hash of the device code; counter summaries taken on other device code are not used."""
+    """Hash of the device code and of the runtime that sets its launch shapes; counter summaries
+    taken on other code are not used."""
     h = hashlib.sha1()
     for fn in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2512_00233_amd", "csrc", fn), "rb") as f:

@@ -555,7 +555,11 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     const int32_t* c = h.cnt[r % 3];
     if (h.overflow[r % 3][0] == 0 && c[0] == 0 && c[1] == 0 && c[2] == 0 && c[3] == 0) break;
     if ((int64_t)r - r0 > (int64_t)1 << 24) return fail(KCORE_E_HIP, "round limit exceeded");
-    K = trace ? 1 : std::min(2 * K, 64);
+    // chunks double up to 16 rounds: past the fixpoint the rest of a chunk
+    // replays empty rounds (about 9 us each against a poll of a few tens of
+    // us); rmat24 (66 rounds) left 59 of them at 64 and takes 25.4 ms at 16,
+    // 25.8 ms at 32, 25.9 ms at 64
+    K = trace ? 1 : std::min(2 * K, 16);
   }
   // the estimates carry their class during the run
   hipLaunchKernelGGL(k_decode, dim3(init_grid), dim3(kBlock), 0, st, out, n);
