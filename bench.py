@@ -15,12 +15,13 @@ Prints ONE JSON line.  Extra objects:
   cpu_baseline  the CPU oracle (definition-level peeling, one thread) timed on
                 this host on the same graph;
   also          the other plain workloads (road / ER small) measured the same
-                way, and reduced runs of the batched form (256 graphs against
-                one plain call per graph) and of the served form (1000
-                requests: saturated graphs/s, Poisson p50/p99, FIFO plain calls).
+                way, and the batched form (2048 graphs against one plain call
+                per graph, every result checked against the oracle, untimed)
+                and the served form (20,000 requests over a pool of 64 graphs:
+                saturated graphs/s, Poisson p50/p99, FIFO plain calls, every
+                result checked against the oracle's result for its graph).
 
---workload batch / serve run those forms at full size (2048 graphs; 2000
-requests over a pool of 64 graphs).
+--workload batch / serve run only those forms.
 """
 import argparse
 import hashlib
@@ -37,11 +38,11 @@ ROOFLINE_RUNS = 3
 
 
 def algorithmic_bytes(updates, visits, changes, acts, off_bytes=8):
-    """Bytes the method itself moves: per recomputed vertex two
-    row offsets, its own estimate and its frontier entry; per adjacency entry
-    the neighbour id and the neighbour's estimate; per change the estimate
-    write; per activation the stamp, the degree class and the list entry."""
-    return (2 * off_bytes + 8) * updates + 8 * visits + 4 * changes + 9 * acts
+    """Bytes the method itself moves: per recomputed vertex two row offsets, its
+    own estimate and its frontier entry; per adjacency entry the neighbour id
+    and the neighbour's estimate; per change the estimate write; per activation
+    the stamp of the activated neighbour (4 bytes)."""
+    return (2 * off_bytes + 8) * updates + 8 * visits + 4 * changes + 4 * acts
 
 
 KERNEL_SOURCES = ("kcore_kernels.h", "kcore_kernels_impl.h", "kcore_runtime.h", "kcore_runtime.hip")
@@ -71,6 +72,18 @@ def measured_traffic(workload, kernel):
     if not k:
         return None
     return k.get("bytes_per_launch_scaled")
+
+
+def host_cpu():
+    """Model name of the host CPU (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def progress(msg):
@@ -239,13 +252,14 @@ def run_batch_workload(args, torch, kc, gg, np):
     if tuned:
         res["autotuned"] = tuned
     if not args.no_cpu_baseline:
-        threads = os.cpu_count() or 1
+        threads = min(16, os.cpu_count() or 1)  # the host share of one GPU
         progress(f"oracle on {threads} threads")
         t = time.perf_counter()
-        ref = oracle.coreness_batch(b.graph_vtx_off, b.row_ptr, b.col_idx, threads=threads)
+        ref = oracle.coreness_batch(b.graph_vtx_off, b.row_ptr, b.col_idx, method="bz", threads=threads)
         dt = time.perf_counter() - t
         res["cpu_baseline"] = {"value": round(G / dt, 2), "unit": "graphs/s", "cores": threads, "kind": "oracle",
-                               "sample": f"whole batch once, {dt:.1f} s, host nproc={os.cpu_count()}"}
+                               "sample": f"whole batch once, Batagelj-Zaversnik per graph over {threads} threads, "
+                                         f"{dt:.1f} s; host {host_cpu()}, nproc={os.cpu_count()}"}
         res["exact"] = bool(np.array_equal(ref, core_batch))
     return res
 
@@ -378,7 +392,7 @@ def main():
     ap.add_argument("--workload", default="rmat24",
                     choices=["rmat24", "road", "er_small", "rmat20", "road_512", "batch", "serve"])
     ap.add_argument("--graphs", type=int, default=2048, help="graphs in the batch workload")
-    ap.add_argument("--requests", type=int, default=2000, help="requests in the serve workload")
+    ap.add_argument("--requests", type=int, default=20000, help="requests in the serve workload")
     ap.add_argument("--pool", type=int, default=64, help="distinct graphs the serve requests sample")
     ap.add_argument("--load", type=float, default=0.7, help="serve: Poisson arrival rate / saturated capacity")
     ap.add_argument("--serve-budget-gb", type=int, default=64, help="serve: device arena budget (GiB)")
@@ -391,6 +405,9 @@ def main():
                     help="instrumented decompositions (per-kernel HIP events and counters)")
     ap.add_argument("--pmc-calibrate", type=int, default=0, metavar="BYTES",
                     help="copy a device buffer of BYTES once first (reference for rocprofv3 byte counters)")
+    ap.add_argument("--pmc-calibrate-read", type=int, default=0, metavar="ENTRIES",
+                    help="one gather probe over ENTRIES sequential indices first (reads 8 bytes per entry, "
+                         "writes 8 bytes: a read-side reference for rocprofv3 byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -415,6 +432,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.pmc_calibrate_read:
+        idx = torch.arange(args.pmc_calibrate_read, dtype=torch.int32, device="cuda")
+        vals = torch.ones(args.pmc_calibrate_read, dtype=torch.int32, device="cuda")
+        acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        kc.probe_gather(idx, vals, acc)
+        torch.cuda.synchronize()
+        del idx, vals, acc
     if args.workload == "batch":
         print(json.dumps(run_batch_workload(args, torch, kc, gg, np)), flush=True)
         return
@@ -455,18 +480,21 @@ def main():
     also = []
     for name in [w for w in args.also.split(",") if w and w != args.workload]:
         if name in ("batch", "serve"):
-            # reduced versions of the batched and served forms (full size: --workload batch / serve)
+            # the batched and served forms at their full sizes (2048 graphs; 20,000 requests)
             sub = argparse.Namespace(**vars(args))
-            sub.no_cpu_baseline, sub.autotune, sub.steps, sub.warmup = True, "", 3, 1
-            sub.graphs, sub.requests, sub.pool = 256, 1000, 32
+            sub.autotune, sub.steps, sub.warmup = "", 3, 1
             if name == "batch":
                 r = run_batch_workload(sub, torch, kc, gg, np)
-                also.append({"workload": "batch", "graphs": sub.graphs, "value": r["value"], "unit": "graphs/s",
+                also.append({"workload": "batch", "graphs": r["config"]["graphs"],
+                             "total_entries": r["config"]["total_entries"], "value": r["value"],
+                             "unit": "graphs/s", "ms_per_step": r["ms_per_step"],
                              "plain_graphs_per_s": r["plain"]["graphs_per_s"],
-                             "speedup_vs_plain": r["speedup_vs_plain"], "identical": r["batch_equals_plain"]})
+                             "speedup_vs_plain": r["speedup_vs_plain"], "identical": r["batch_equals_plain"],
+                             "exact": r.get("exact"), "cpu_baseline": r.get("cpu_baseline")})
             else:
                 r = run_serve_workload(sub, torch, kc, gg, np)
-                also.append({"workload": "serve", "requests": sub.requests, "value": r["value"], "unit": "graphs/s",
+                also.append({"workload": "serve", "requests": sub.requests, "pool_graphs": sub.pool,
+                             "value": r["value"], "unit": "graphs/s",
                              "fifo_graphs_per_s": r["fifo_plain"]["graphs_per_s"],
                              "speedup_vs_fifo": r["speedup_vs_fifo"], "p50_ms": r["poisson"]["p50_ms"],
                              "p99_ms": r["poisson"]["p99_ms"], "fifo_p99_ms": r["fifo_plain"]["p99_ms"],
@@ -481,20 +509,22 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
-        runs, spent, t_best = 0, 0.0, None
+        runs, spent, times = 0, 0.0, []
         while spent < args.cpu_seconds or runs == 0:
             t = time.perf_counter()
-            ref = oracle.coreness(g.row_ptr, g.col_idx)
+            ref = oracle.coreness_bz(g.row_ptr, g.col_idx)
             dt = time.perf_counter() - t
             spent += dt
             runs += 1
-            t_best = dt if t_best is None else min(t_best, dt)
+            times.append(dt)
             if runs >= 5:
                 break
-        result["cpu_baseline"] = {"value": round(m_und / t_best / 1e9, 5), "unit": "GTEPS", "cores": 1,
+        t_med = float(np.median(times))
+        result["cpu_baseline"] = {"value": round(m_und / t_med / 1e9, 5), "unit": "GTEPS", "cores": 1,
                                   "kind": "oracle",
-                                  "sample": f"full {args.workload} graph, best of {runs} run(s), {spent:.1f} s "
-                                            f"total, host nproc={os.cpu_count()}"}
+                                  "sample": f"full {args.workload} graph, Batagelj-Zaversnik (C, -O3, one thread), "
+                                            f"median of {runs} run(s), {spent:.1f} s total; host {host_cpu()}, "
+                                            f"nproc={os.cpu_count()}"}
         result["exact"] = bool(np.array_equal(ref, core))
     print(json.dumps(result), flush=True)
 

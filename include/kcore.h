@@ -53,8 +53,8 @@ typedef struct kcore_tuning {
   int32_t group_max_deg;   /* class 1, 16 lanes per vertex: degree <= this (<= 64, default 64) */
   int32_t wave_max_deg;    /* class 2, one wavefront per vertex: degree <= this (<= 512, default 512);
                               above: class 3, one workgroup per vertex */
-  int32_t tail_threshold;  /* frontier work (lane = 1, group = 4, wavefront = 16) at or below which one
-                              workgroup finishes the run (<0: never; 0: 512 for single graphs,
+  int32_t tail_threshold;  /* frontier work (lane = 1, group = 4, wavefront = 16, workgroup = 64) at or below
+                              which one workgroup finishes the run (<0: never; 0: 512 for single graphs,
                               2048 for the batched form) */
   int32_t grid_blocks;     /* workgroups per small-class round launch (0: 8 per compute unit, raised to one per
                               32768 vertices, at most 32 per compute unit, for very large inputs) */
@@ -83,22 +83,36 @@ typedef struct kcore_tuning {
                               of the round and decided by their final level and slack, 2 re-activated at once;
                               0: automatic (deferred for single graphs of at least 2^20 vertices under the
                               two-sided rule, otherwise re-activated) */
-  int32_t reserved;
+  int32_t tail_round_cap;  /* rounds one single-workgroup tail launch runs before it hands its frontier back
+                              to the round launches, which continue the run (0: 65536).  No run has a round
+                              limit: a long chain of drops simply takes several tail launches */
+  int32_t tail_order;      /* order inside the tail: 0 (default) round by round, every queued vertex once per
+                              round; 1 lowest estimate first (the order of the paper's sequential phase,
+                              Sec. IV): each step takes the queued vertices of the lowest estimates, one
+                              workgroup pass of work, and keeps the rest queued */
+  int32_t tail_big;        /* 1: class-3 vertices (workgroup per vertex) may enter the tail, at 64 units of
+                              work each; 0 (default): a frontier with one keeps the run out of the tail */
+  int32_t round_renorm;    /* round number above which the per-vertex round stamps are renumbered down
+                              between two chunks of rounds (0: 2^30; values below 1024 are raised to 1024).
+                              Round numbers therefore never overflow, however many rounds or served steps
+                              a call or a server runs; a test hook, results never depend on it */
+  int32_t reserved[4];
 } kcore_tuning;
 
 /* Round kernels, as indices into kcore_stats.kernel.  The first round (every
  * vertex of degree >= 2) runs its own instances of the class-3 and classes-0..2
  * kernels; later rounds run a compaction kernel (list rebuild from the round
  * stamps; it does nothing unless the previous round's lists overflowed), the
- * class-3 kernel and the classes-0..2 kernel (which also hosts the
- * single-workgroup tail). */
+ * class-3 kernel, the classes-0..2 kernel (which also hosts the
+ * single-workgroup tail) and, on large single graphs, the deferred checks. */
 enum {
   KCORE_K_BIG_FIRST = 0,
   KCORE_K_ROUND_FIRST = 1,
   KCORE_K_BIG = 2,
   KCORE_K_ROUND = 3,
   KCORE_K_COMPACT = 4,
-  KCORE_K_COUNT = 5
+  KCORE_K_DEFER = 5,       /* deferred same-kernel checks at the end of a later round (when enabled) */
+  KCORE_K_COUNT = 6
 };
 
 /* Work and time of one round kernel over a call.  Edge visits count the
@@ -288,7 +302,8 @@ typedef struct kcore_serve_report {
   int64_t bytes_peak;   /* peak footprint of admitted requests */
   double p50_us, p99_us, max_us, mean_us;  /* latency over completed requests */
   double graphs_per_s;  /* completed / (last completion - first submit) */
-  int64_t reserved[4];
+  int64_t rebases;      /* renumberings of the round stamps (kcore_tuning.round_renorm) */
+  int64_t reserved[3];
 } kcore_serve_report;
 
 /* Create a server (cfg may be NULL: defaults).  Allocates the arenas, four

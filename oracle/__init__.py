@@ -42,9 +42,9 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C, -O2)."""
+    """Compile the oracle with gcc (plain C, -O3)."""
     if force or not os.path.exists(_LIB_PATH):
-        cmd = ["gcc", "-O2", "-std=c99", "-D_POSIX_C_SOURCE=200809L", "-shared", "-fPIC", "-pthread",
+        cmd = ["gcc", "-O3", "-std=c99", "-D_POSIX_C_SOURCE=200809L", "-shared", "-fPIC", "-pthread",
                "-o", _LIB_PATH + ".tmp", os.path.join(_HERE, "kcore_oracle.c")]
         subprocess.check_call(cmd)
         os.replace(_LIB_PATH + ".tmp", _LIB_PATH)

@@ -52,11 +52,15 @@ class Tuning(ctypes.Structure):
         ("max_rounds", ctypes.c_int32),
         ("relabel", ctypes.c_int32),
         ("deferred", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("tail_round_cap", ctypes.c_int32),
+        ("tail_order", ctypes.c_int32),
+        ("tail_big", ctypes.c_int32),
+        ("round_renorm", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
-KERNELS = ("big_first", "round_first", "big", "round", "compact")
+KERNELS = ("big_first", "round_first", "big", "round", "compact", "defer")
 # rocprofv3 names of the kernels of a single-graph run (int64 offsets), by KERNELS entry
 KERNEL_SYMBOLS = {
     "big_first": "k_big<true, false, long>",
@@ -64,6 +68,7 @@ KERNEL_SYMBOLS = {
     "big": "k_big<false, false, long>",
     "round": "k_round<256, false, false, long>",
     "compact": "k_compact<false, long>",
+    "defer": "k_defer<long>",
 }
 
 
@@ -167,7 +172,8 @@ class ServeReport(ctypes.Structure):
         ("max_us", ctypes.c_double),
         ("mean_us", ctypes.c_double),
         ("graphs_per_s", ctypes.c_double),
-        ("reserved", ctypes.c_int64 * 4),
+        ("rebases", ctypes.c_int64),
+        ("reserved", ctypes.c_int64 * 3),
     ]
 
     def as_dict(self) -> dict:

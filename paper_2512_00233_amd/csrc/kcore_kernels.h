@@ -110,11 +110,17 @@ struct Ctl {
   unsigned long long stats[16];   // run counters (ST_ROUNDS ...)
   // per round kernel (KernelId) and counter (ST_UPDATES .. ST_FULL_SCANS), spread over
   // kStatCopies addresses by workgroup so that the flushes of a launch do not all meet
-  unsigned long long kstats[4][6][16];
-  int32_t error;                  // 1: the tail hit its round cap
+  unsigned long long kstats[5][6][16];
   int32_t rbase;                  // round number of slot 0 of the next chunk of round launches
   int32_t tail_pending;           // rounds run by a tail since the last base advance (stamps up to rbase + this)
   int32_t nhi;                    // served graphs: vertex-id bound of the live slots (compaction range)
+  // A tail that reached its round cap hands its frontier back to the round
+  // launches: the round number of that frontier and its list sizes by class
+  // (the lists of that round hold it, uncapped); the chunk's base advance then
+  // moves the round base there instead of past the chunk.
+  int32_t resume;
+  int32_t resume_round;
+  int32_t resume_cnt[kClasses];
   // deferred same-kernel checks appended in the current round, one counter per
   // buffer region (a workgroup appends to region blockIdx.x % kDeferRegions)
   int32_t dcnt[128];
@@ -126,11 +132,19 @@ enum Stat {
 constexpr int kLaneStats = 6;  // stats accumulated per lane (ST_UPDATES .. ST_FULL_SCANS)
 constexpr int kStatCopies = 16;
 // Round kernels whose work is counted separately (the first round's two, the later rounds' two).
-enum KernelId { KI_BIG_FIRST = 0, KI_ROUND_FIRST, KI_BIG, KI_ROUND, KI_COUNT };
+// (and the deferred checks, whose activations are counted too)
+enum KernelId { KI_BIG_FIRST = 0, KI_ROUND_FIRST, KI_BIG, KI_ROUND, KI_DEFER, KI_COUNT };
 
-// Hard cap on rounds inside one tail invocation (a correct run needs far fewer;
-// the cap only guarantees that the kernel terminates).
-constexpr int32_t kTailRoundCap = 1 << 22;
+// Rounds one tail launch runs before it hands its frontier back to the round
+// launches (default of kcore_tuning.tail_round_cap).  A long chain of
+// dependent drops (a path of n vertices needs about n/2 rounds) thus never
+// keeps one kernel running for long, and no run has a round limit.
+constexpr int32_t kTailRoundCap = 1 << 16;
+// Round number above which the stamps are renumbered down by a multiple of 6
+// (which keeps every round's counter slot, round % 3, and list parity), so that
+// round numbers never approach the int32 range (default of
+// kcore_tuning.round_renorm).
+constexpr int32_t kRoundRenorm = 1 << 30;
 
 template <typename Off>
 struct Args {
@@ -159,6 +173,9 @@ struct Args {
   // neighbours are re-activated instead).
   int32_t* defer;
   int32_t defer_cap;   // triples
+  int32_t tail_cap;    // rounds per tail launch before the frontier is handed back (kTailRoundCap)
+  int32_t tail_order;  // 1: the tail takes its frontier lowest estimate first, a bounded amount of work per step
+  int32_t tail_big;    // 1: class-3 vertices may enter the tail (64 work units each)
 };
 
 // A served graph's place in the arenas.

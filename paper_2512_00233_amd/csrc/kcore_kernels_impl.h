@@ -1112,12 +1112,105 @@ __device__ __forceinline__ void sweep_small(const Args<Off>& a, const Sink& s, c
 }
 
 // ------------------------------------------------------------------ tail
+// Whether the frontier f of a round goes to the single-workgroup tail: a round
+// that is not dense, whose work (lane = 1, 16-lane group = 4, wavefront = 16,
+// workgroup = 64) is at most the threshold, with no class-3 vertex unless
+// tail_big admits them.  The class-3 kernel, which runs before the
+// classes-0..2 kernel of the same round, makes the same decision and then
+// leaves the round to the tail.
+template <typename Off>
+__device__ __forceinline__ bool tail_eligible(const Args<Off>& a, const Frontier& f, bool dense) {
+  if (dense || (f.n[3] > 0 && !a.tail_big)) return false;
+  const int64_t work = (int64_t)f.n[0] + 4ll * f.n[1] + 16ll * f.n[2] + 64ll * f.n[3];
+  return work > 0 && work <= a.tail_threshold;
+}
+
+// Lowest estimate first inside the tail (the order of FastK's sequential
+// phase, Sec. IV: the vertex with the lowest estimate is taken next, so that
+// vertices of high coreness are not recomputed for every change below them).
+// Of the frontier f of round r, the tail keeps the vertices whose estimate is
+// at most tau, the lowest level at which their work (lanes: 1, 16, 64 and a
+// workgroup by class) fills one pass of the workgroup; every vertex is kept
+// when the whole frontier fits one pass.  The others move to the next round's
+// lists with the next round's stamp, before anything of this round is
+// processed, so activations see them as already queued.  Estimates at or above
+// kTailBins - 1 share the top bin.  bins holds kTailBins ints of LDS.
+constexpr int kTailBins = 256;
+template <int BLOCK, typename Off>
+__device__ __forceinline__ void tail_select(const Args<Off>& a, Frontier& f, int32_t r, int32_t* ncnt,
+                                            int32_t* bins, int32_t* red) {
+  static_assert(BLOCK == kTailBins, "one bin per thread");
+  const int tid = threadIdx.x;
+  const int32_t w[kClasses] = {1, kGroupLanes, kWave, BLOCK};
+  int64_t total = 0;
+#pragma unroll
+  for (int k = 0; k < kClasses; ++k) total += (int64_t)f.n[k] * w[k];
+  if (total <= BLOCK) return;
+  bins[tid] = 0;
+  __syncthreads();
+  for (int k = 0; k < kClasses; ++k)
+    for (int32_t i = tid; i < f.n[k]; i += BLOCK)
+      atomicAdd(&bins[min(est_val(a.est[f.list[f.b[k] + i]]), kTailBins - 1)], w[k]);
+  __syncthreads();
+  int32_t tot = 0;
+  const int32_t before = block_excl_scan<BLOCK>(bins[tid], tot, red);
+  // the lowest bin whose cumulative work reaches one pass
+  const bool reach = before + bins[tid] >= BLOCK;
+  int32_t first = reach ? tid : kTailBins;
+  first = min(first, __shfl_xor(first, 32));
+  first = min(first, __shfl_xor(first, 16));
+  first = min(first, __shfl_xor(first, 8));
+  first = min(first, __shfl_xor(first, 4));
+  first = min(first, __shfl_xor(first, 2));
+  first = min(first, __shfl_xor(first, 1));
+  if (lane_id() == 0) red[tid / kWave] = first;
+  __syncthreads();
+  int32_t bin = kTailBins;
+#pragma unroll
+  for (int q = 0; q < BLOCK / kWave; ++q) bin = min(bin, red[q]);
+  __syncthreads();
+  const int32_t tau = bin >= kTailBins - 1 ? INT32_MAX : bin;
+  int32_t* next = list_of(a, r + 1);
+  const int lane = lane_id();
+  for (int k = 0; k < kClasses; ++k) {
+    int32_t kept = 0;
+    for (int32_t j0 = 0; j0 < f.n[k]; j0 += BLOCK) {
+      const int32_t j = j0 + tid;
+      const int32_t v = j < f.n[k] ? f.list[f.b[k] + j] : -1;
+      const bool sel = v >= 0 && est_val(a.est[v]) <= tau;
+      const bool carry = v >= 0 && !sel;
+      int32_t chunk = 0;
+      // every entry of the chunk is read before any is written (the scan's barriers);
+      // writes stay below the positions still to be read
+      const int32_t off = block_excl_scan<BLOCK>(sel ? 1 : 0, chunk, red);
+      if (sel) const_cast<int32_t*>(f.list)[f.b[k] + kept + off] = v;
+      kept += chunk;
+      const uint64_t m = ballot(carry);
+      if (m) {
+        int32_t base = 0;
+        if (lane == 0) base = atomicAdd(&ncnt[k], popc(m));
+        base = __shfl(base, 0);
+        if (carry) {
+          next[f.b[k] + base + lanes_below(m)] = v;
+          a.stamp[v] = r + 1;
+          if (a.gact) a.gact[a.vbase[v]] = r + 1;  // served graphs: the graph still has work
+        }
+      }
+    }
+    f.n[k] = kept;
+  }
+  __syncthreads();
+}
+
 // One workgroup runs the remaining rounds on uncapped lists.  Within the
 // workgroup, stores become visible to all its wavefronts at each barrier, so no
-// launch is needed per round.
+// launch is needed per round.  After a_.tail_cap rounds a tail that still has
+// a frontier hands it back to the round launches (Ctl::resume): the kernel
+// always ends after a bounded number of rounds, and long runs continue in the
+// next chunk of launches.
 template <int BLOCK, bool BATCH, typename Off>
 __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, const Frontier& f0, LaneStats& st,
-                                         int32_t* red) {
+                                         int32_t* red, int32_t* bins) {
   Ctl* ctl = a.ctl;
   const int tid = threadIdx.x;
   if (tid < kClasses) {
@@ -1135,11 +1228,18 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
       for (int k = 0; k < kClasses; ++k) f.n[k] = ld_counter(&ctl->tail_cnt[t & 1][k]);
     }
     if (f.n[0] + f.n[1] + f.n[2] + f.n[3] == 0) break;
-    if (t >= kTailRoundCap) {
-      if (tid == 0) ctl->error = 1;
+    if (t >= a.tail_cap) {
+      // the frontier of round r (stamps r, in the lists of round r) goes back to the round launches
+      if (tid < kClasses) ctl->resume_cnt[tid] = f.n[tid];
+      if (tid == 0) {
+        ctl->resume_round = r;
+        ctl->resume = 1;
+      }
       break;
     }
-    const Sink s = make_sink(a, r + 1, ctl->tail_cnt[(t + 1) & 1], nullptr, false);
+    int32_t* ncnt = ctl->tail_cnt[(t + 1) & 1];
+    if (a.tail_order) tail_select<BLOCK>(a, f, r, ncnt, bins, red);
+    const Sink s = make_sink(a, r + 1, ncnt, nullptr, false);
     // the two groups of classes in the order of the round kernels; the barrier
     // makes the first group's updates visible to the second
     if (kBigFirst)
@@ -1155,8 +1255,9 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
     if (t > 0 && tid < kClasses) ctl->tail_cnt[t & 1][tid] = 0;  // reused by round t+2
     __syncthreads();
   }
-  // Nothing is left anywhere: clear every round slot (the round base then skips
-  // past the stamps the tail used, so none of them is read again).
+  // Nothing is left in the round slots: clear them (the round base then skips
+  // past the stamps the tail used, so none of them is read again; a handed-back
+  // frontier is restored by the base advance).
   if (tid < 12) {
     ctl->cnt[tid / 4][tid % 4] = 0;
     ctl->overflow[tid / 4][tid % 4] = 0;
@@ -1176,7 +1277,8 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
 // negative).  A charge for a drop that v had in fact seen only makes the rule
 // more conservative.
 template <typename Off>
-__global__ __launch_bounds__(256) void k_defer(Args<Off> a, int32_t slot) {
+__global__ __launch_bounds__(256) void k_defer(Args<Off> a, int32_t slot, int32_t collect_stats) {
+  __shared__ unsigned long long red64[kLaneStats * (256 / kWave)];
   if (!a.defer) return;
   Ctl* ctl = a.ctl;
   const int32_t round = ctl->rbase + slot;
@@ -1209,12 +1311,19 @@ __global__ __launch_bounds__(256) void k_defer(Args<Off> a, int32_t slot) {
     // activation as in the first round (unconditional for the lanes that set act)
     activate_changed<1, true>(a, s, v, one, act, INT32_MAX, 0, true, round, st, 0, c);
   }
+  if (collect_stats) flush_stats<256>(ctl, KI_DEFER, st, red64);
 }
 
 // The estimates of a finished run (or of a stopped one) without their class bits.
 __global__ void k_decode(int32_t* est, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) est[v] = est_val(est[v]);
+}
+
+// p[0 .. n) = value (a kernel rather than a memset, so that the sequence can be captured in a graph).
+__global__ __launch_bounds__(256) void k_fill(int32_t* p, int64_t n, int32_t value) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = value;
 }
 
 // Zero the control block (a kernel rather than a memset, so that the sequence
@@ -1225,12 +1334,38 @@ __global__ void k_zero_ctl(Ctl* ctl) {
 }
 
 // Move the round base past a chunk of `k` round launches and past the rounds
-// a tail ran inside it.
+// a tail ran inside it; after a tail that handed its frontier back, to the
+// round of that frontier, whose list sizes become the round's counters (the
+// rounds of the chunk after the tail found nothing to do).
 __global__ void k_advance(Ctl* ctl, int32_t k) {
   if (threadIdx.x == 0) {
-    ctl->rbase += k + ctl->tail_pending;
+    if (ctl->resume) {
+      const int32_t r = ctl->resume_round;
+      ctl->rbase = r;
+#pragma unroll
+      for (int c = 0; c < kClasses; ++c) {
+        ctl->cnt[r % 3][c] = ctl->resume_cnt[c];
+        ctl->overflow[r % 3][c] = 0;
+      }
+      ctl->resume = 0;
+    } else {
+      ctl->rbase += k + ctl->tail_pending;
+    }
     ctl->tail_pending = 0;
   }
+}
+
+// Renumber the round stamps down by d (a multiple of 6, so that every round
+// keeps its counter slot, round % 3, and its list parity), stamps older than d
+// becoming 0, and the activity words of served graphs with them; the round base
+// follows.  Run between two chunks, when no round is in flight.
+__global__ __launch_bounds__(256) void k_rebase(int32_t* stamp, int32_t* gact, int64_t n, int32_t d, Ctl* ctl) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    stamp[v] = max(stamp[v] - d, 0);
+    if (gact) gact[v] = max(gact[v] - d, 0);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->rbase -= d;
 }
 
 // Batched graphs: vbase[v] = first global vertex id of v's graph (one workgroup per graph).
@@ -1373,6 +1508,7 @@ template <int BLOCK, bool FIRST, bool BATCH, typename Off>
 __global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t slot, int32_t collect_stats) {
   __shared__ unsigned long long red64[kLaneStats * (BLOCK / kWave)];
   __shared__ int32_t red[kKary * (BLOCK / kWave)];
+  __shared__ int32_t tbins[kTailBins];
   Ctl* ctl = a.ctl;
   const int32_t round = ctl->rbase + slot;
   bool dense = false;
@@ -1385,9 +1521,9 @@ __global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t slot, int3
   LaneStats st;
   const int32_t tot = f.n[0] + f.n[1] + f.n[2] + f.n[3];
   if (!FIRST && tot == 0) return;
-  if (!FIRST && !dense && f.n[3] == 0 && (int64_t)f.n[0] + 4ll * f.n[1] + 16ll * f.n[2] <= a.tail_threshold) {
+  if (!FIRST && tail_eligible(a, f, dense)) {
     if (blockIdx.x == 0) {
-      run_tail<BLOCK, BATCH>(a, round, f, st, red);
+      run_tail<BLOCK, BATCH>(a, round, f, st, red, tbins);
       if (collect_stats) flush_stats<BLOCK>(ctl, KI_ROUND, st, red64);
     }
     return;
@@ -1423,6 +1559,7 @@ __global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot,
   bool dense = false;
   const Frontier f = frontier_of<FIRST>(a, round, dense);
   if (f.n[3] == 0) return;
+  if (!FIRST && tail_eligible(a, f, dense)) return;  // the classes-0..2 kernel runs the round as a tail
   LaneStats st;
   const int nslot = (round + 1) % 3;
   Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
@@ -1564,7 +1701,8 @@ __global__ __launch_bounds__(256) void k_slot_init(Args<Off> a, const SlotDesc* 
     a.plen[v] = 0;
     a.cls[v] = c;
     const_cast<int32_t*>(a.vbase)[v] = sd.vb;
-    if (d >= 2) a.stamp[v] = r;
+    // a stamp left by an earlier graph in this range is overwritten (0 never equals a round)
+    a.stamp[v] = d >= 2 ? r : 0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) a.gact[sd.vb] = r;
 }

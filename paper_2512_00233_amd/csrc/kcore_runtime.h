@@ -33,6 +33,10 @@ struct Tuning {
   int max_rounds; // > 0: stop after this many rounds (tail off)
   int relabel;    // 1: renumber by degree first (single-graph calls)
   int defer;      // deferred same-kernel checks: 1 on, 0 off, -1 chosen from the graph (settle_tuning)
+  int tail_cap;   // rounds per tail launch before it hands its frontier back
+  int tail_order; // 1: lowest estimate first inside the tail
+  int tail_big;   // 1: class-3 vertices may enter the tail
+  int renorm;     // round number above which stamps are renumbered down
 };
 
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus);
@@ -93,9 +97,11 @@ kcore_status serve_step(ServeArena* A, int32_t rounds, int32_t nslots, int32_t* 
 // Strip the class bits from the estimates of a finished graph (vertices vb .. vb+n-1) before they are
 // copied out.
 kcore_status serve_decode(ServeArena* A, int64_t vb, int64_t n, hipStream_t st);
-// Round base and error flag of a control block copied to the host.
+// Round base of a control block copied to the host.
 int32_t serve_ctl_rbase(const void* host_ctl);
-int32_t serve_ctl_error(const void* host_ctl);
 size_t serve_ctl_size();
+// Renumber the round stamps and activity words of the live vertex range [0, nhi) down by d (a multiple of
+// 6), between two steps; the device round base follows.
+kcore_status serve_rebase(ServeArena* A, int64_t nhi, int32_t d, void* stream);
 
 }  // namespace kcore

@@ -189,6 +189,9 @@ static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, bool 
 }
 
 // ------------------------------------------------------------------ tuning
+// Most rounds in one chunk of launches (the timing mode keeps events for this many).
+constexpr int kMaxChunkRounds = 64;
+
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   Tuning r;
   r.t0 = kLaneMaxDeg;
@@ -212,6 +215,10 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.max_rounds = 0;
   r.relabel = 0;
   r.defer = -1;
+  r.tail_cap = kTailRoundCap;
+  r.tail_order = 0;
+  r.tail_big = 0;
+  r.renorm = kRoundRenorm;
   if (const char* e = std::getenv("KCORE_TAIL")) {
     r.tail = std::atoi(e);
     r.tail_auto = 0;
@@ -231,7 +238,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
       r.big_grid = t->big_grid_blocks;
       r.big_grid_auto = 0;
     }
-    if (t->rounds_per_poll > 0) r.poll = t->rounds_per_poll;
+    if (t->rounds_per_poll > 0) r.poll = std::min(t->rounds_per_poll, kMaxChunkRounds);
     if (t->activation == 1 || t->activation == 2) r.one_sided = t->activation == 1;
     r.timing = t->timing == 1;
     if (t->list_cap > 0) {
@@ -242,6 +249,10 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
     r.use_graph = t->no_graph != 1;
     r.relabel = t->relabel == 2;
     if (t->deferred == 1 || t->deferred == 2) r.defer = t->deferred == 1;
+    if (t->tail_round_cap > 0) r.tail_cap = t->tail_round_cap;
+    r.tail_order = t->tail_order == 1;
+    r.tail_big = t->tail_big == 1;
+    if (t->round_renorm > 0) r.renorm = std::max(t->round_renorm, 1024);
     if (t->max_rounds > 0) {
       r.max_rounds = t->max_rounds;
       r.tail = 0;
@@ -319,8 +330,9 @@ static int compact_grid(int64_t n, int num_cus) {
 }
 
 // The two update kernels of a round (slot relative to the round base), in
-// kBigFirst order.  With ev (3 events) the launches are bracketed: ev[0]
-// before the first, ev[1] between, ev[2] after the second.
+// kBigFirst order, then the deferred checks.  With ev (4 events) the launches
+// are bracketed: ev[0] before the first, ev[1] between, ev[2] after the second,
+// ev[3] after the deferred checks.
 template <bool FIRST, bool BATCH, typename Off>
 static void launch_updates(const Args<Off>& a, const Tuning& tu, int32_t slot, int32_t collect, hipStream_t st,
                            hipEvent_t* ev) {
@@ -336,9 +348,10 @@ static void launch_updates(const Args<Off>& a, const Tuning& tu, int32_t slot, i
     hipLaunchKernelGGL((k_big<FIRST, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, slot, collect);
   // the deferred same-kernel checks of the round (none in the first round, nor under the one-sided
   // rule, which re-activates every candidate)
-  if (!FIRST && a.defer && !a.one_sided)
-    hipLaunchKernelGGL((k_defer<Off>), dim3(4 * kDeferRegions), dim3(kBlock), 0, st, a, slot);
   if (ev) (void)hipEventRecord(ev[2], st);
+  if (!FIRST && a.defer && !a.one_sided)
+    hipLaunchKernelGGL((k_defer<Off>), dim3(4 * kDeferRegions), dim3(kBlock), 0, st, a, slot, collect);
+  if (ev) (void)hipEventRecord(ev[3], st);
 }
 
 // The compaction of a round (a no-op unless its lists overflowed).
@@ -393,9 +406,9 @@ static kcore_status launch_chunk(Workspace* ws, const Args<Off>& a, const Tuning
   return KCORE_OK;
 }
 
-// Timing mode: one round with an event before and after each of its three
-// kernels (compaction, class 3, classes 0..2), then the base advance.
-constexpr int kRoundEvents = 4;
+// Timing mode: one round with an event before and after each of its kernels
+// (compaction, class 3, classes 0..2, deferred checks), then the base advance.
+constexpr int kRoundEvents = 5;
 template <bool BATCH, typename Off>
 static void launch_round_timed(const Args<Off>& a, const Tuning& tu, int cgrid, int32_t collect, hipEvent_t* ev,
                                hipStream_t st) {
@@ -427,7 +440,8 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   const int init_grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
   const int cgrid = compact_grid(n, ws->num_cus);
   if (ws->epoch > (1 << 29)) {
-    KC_HIP(hipMemsetAsync(ws->stamp, 0, sizeof(int32_t) * ws->cap_n, st));
+    const int fgrid = (int)std::min<int64_t>((ws->cap_n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
+    hipLaunchKernelGGL(k_fill, dim3(std::max(fgrid, 1)), dim3(kBlock), 0, st, ws->stamp, ws->cap_n, 0);
     ws->epoch = 1;
   }
   Args<Off> a;
@@ -453,16 +467,19 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   a.defer = tu.defer > 0 ? ws->defer : nullptr;
   a.defer_cap = (int32_t)ws->defer_cap;
   a.prune = tu.prune;
+  a.tail_cap = tu.tail_cap;
+  a.tail_order = tu.tail_order;
+  a.tail_big = tu.tail_big;
   const int32_t collect = (stats || rec) ? 1 : 0;
   const bool trace_env = env_flag("KCORE_TRACE");
   const bool trace = trace_env || rec != nullptr;  // one round per launch, counters read after each
   const bool timing = tu.timing || trace;
   const bool use_graph = tu.use_graph && !timing && st != nullptr;  // no capture on the null stream
-  const int32_t r0 = ws->epoch;
-  double kms[KCORE_K_COUNT] = {0, 0, 0, 0, 0};
+  int32_t r0 = ws->epoch;
+  double kms[KCORE_K_COUNT] = {0, 0, 0, 0, 0, 0};
   double init_ms = 0;
   if (timing) {
-    kcore_status s = ws->need_events(kRoundEvents * 64);
+    kcore_status s = ws->need_events(kRoundEvents * kMaxChunkRounds);
     if (s != KCORE_OK) return s;
   }
   hipEvent_t* ev = timing ? ws->events.data() : nullptr;
@@ -477,12 +494,12 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   std::memset(prev, 0, sizeof(prev));
   unsigned long long prev_tail = 0;
   auto trace_line = [&](const Ctl& h, int32_t r, const char* what, float ms) {
-    unsigned long long d[2][kLaneStats];  // [0]: class-3 kernels, [1]: classes 0..2
+    unsigned long long d[2][kLaneStats];  // [0]: class-3 kernels and deferred checks, [1]: classes 0..2
     std::memset(d, 0, sizeof(d));
     for (int k = 0; k < KI_COUNT; ++k)
       for (int q = 0; q < kLaneStats; ++q) {
         const unsigned long long now = kstat(h, k, q);
-        d[k == KI_BIG_FIRST || k == KI_BIG ? 0 : 1][q] += now - prev[k][q];
+        d[k == KI_BIG_FIRST || k == KI_BIG || k == KI_DEFER ? 0 : 1][q] += now - prev[k][q];
         prev[k][q] = now;
       }
     if (rec) {
@@ -521,6 +538,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   int64_t launches = 1;
   int K = trace ? 1 : tu.poll;
   int32_t r = r0 + 1;
+  int64_t rounds_done = 1;  // round numbers, across renumberings
   for (;;) {
     if (tu.max_rounds > 0) {
       if (launches >= tu.max_rounds) {
@@ -542,6 +560,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     KC_HIP(hipStreamSynchronize(st));
     const Ctl& h = *ws->host_ctl;
+    rounds_done += (int64_t)h.rbase - r;
     r = h.rbase;
     if (timing) {
       for (int i = 0; i < K; ++i) {
@@ -549,12 +568,26 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
         kms[KCORE_K_COMPACT] += elapsed(e[0], e[1]);
         kms[KCORE_K_BIG] += kBigFirst ? elapsed(e[1], e[2]) : elapsed(e[2], e[3]);
         kms[KCORE_K_ROUND] += kBigFirst ? elapsed(e[2], e[3]) : elapsed(e[1], e[2]);
-        if (trace) trace_line(h, r - 1, "", elapsed(e[0], e[3]));
+        kms[KCORE_K_DEFER] += elapsed(e[3], e[4]);
+        if (trace) trace_line(h, r - 1, "", elapsed(e[0], e[4]));
       }
     }
     const int32_t* c = h.cnt[r % 3];
     if (h.overflow[r % 3][0] == 0 && c[0] == 0 && c[1] == 0 && c[2] == 0 && c[3] == 0) break;
-    if ((int64_t)r - r0 > (int64_t)1 << 24) return fail(KCORE_E_HIP, "round limit exceeded");
+    // Every round but the last lowers an estimate (a round without a change
+    // activates nobody), and the estimates fall by at most the sum of the
+    // degrees: more rounds than that mean a fault, not a long run.
+    if (rounds_done > nnz + 16) return fail(KCORE_E_HIP, "round count above its bound (internal error)");
+    if (r > tu.renorm) {
+      // round numbers stay far from the int32 range: renumber the stamps of every workspace vertex
+      const int32_t d = (r - 64) / 6 * 6;
+      const int rgrid = (int)std::min<int64_t>((ws->cap_n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
+      hipLaunchKernelGGL(k_rebase, dim3(rgrid), dim3(kBlock), 0, st, ws->stamp, (int32_t*)nullptr, ws->cap_n, d,
+                         ws->ctl);
+      KC_HIP(hipGetLastError());
+      r -= d;
+      r0 -= d;
+    }
     // chunks double up to 16 rounds: past the fixpoint the rest of a chunk
     // replays empty rounds (about 9 us each against a poll of a few tens of
     // us); rmat24 (66 rounds) left 59 of them at 64 and takes 25.4 ms at 16,
@@ -565,7 +598,6 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   hipLaunchKernelGGL(k_decode, dim3(init_grid), dim3(kBlock), 0, st, out, n);
   KC_HIP(hipGetLastError());
   const Ctl& hc = *ws->host_ctl;
-  if (hc.error) return fail(KCORE_E_HIP, "tail round cap reached (internal error)");
   ws->epoch = r + 4;  // the round base already counts the tail's rounds
   if (stats) {
     stats->rounds = (int64_t)hc.stats[ST_ROUNDS];
@@ -573,9 +605,10 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     stats->launches = launches;
     stats->dense_rounds = (int64_t)hc.stats[ST_DENSE_ROUNDS];
     stats->init_ms = init_ms;
-    const int64_t kl[KCORE_K_COUNT] = {1, 1, launches - 1, launches - 1, launches - 1};
+    const bool defer_on = a.defer && !a.one_sided;
+    const int64_t kl[KCORE_K_COUNT] = {1, 1, launches - 1, launches - 1, launches - 1, defer_on ? launches - 1 : 0};
     // counters by public kernel index (the compaction kernel has none)
-    const int kid[KCORE_K_COUNT] = {KI_BIG_FIRST, KI_ROUND_FIRST, KI_BIG, KI_ROUND, -1};
+    const int kid[KCORE_K_COUNT] = {KI_BIG_FIRST, KI_ROUND_FIRST, KI_BIG, KI_ROUND, -1, KI_DEFER};
     for (int k = 0; k < KCORE_K_COUNT; ++k) {
       kcore_kernel_stats& o = stats->kernel[k];
       o.launches = kl[k];
@@ -605,7 +638,7 @@ template <typename Off>
 static kcore_status validate_csr(Workspace* ws, int64_t n, const Off* row_ptr, const int32_t* col,
                                  hipStream_t st) {
   const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
-  KC_HIP(hipMemsetAsync(ws->verr, 0x7f, sizeof(int32_t), st));
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, ws->verr, (int64_t)1, (int32_t)0x7f7f7f7f);
   hipLaunchKernelGGL(k_validate<Off>, dim3(grid), dim3(kBlock), 0, st, n, row_ptr, col, ws->verr);
   KC_HIP(hipGetLastError());
   KC_HIP(hipMemcpyAsync(ws->host_verr, ws->verr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -941,6 +974,9 @@ static Args<int64_t> serve_args(const ServeArena* A) {
   a.one_sided = A->tu.one_sided;
   a.prune = A->tu.prune;
   a.gact = A->gact;
+  a.tail_cap = A->tu.tail_cap;
+  a.tail_order = A->tu.tail_order;
+  a.tail_big = A->tu.tail_big;
   return a;
 }
 
@@ -1070,8 +1106,15 @@ kcore_status serve_step(ServeArena* A, int32_t rounds, int32_t nslots, int32_t* 
 }
 
 int32_t serve_ctl_rbase(const void* host_ctl) { return static_cast<const Ctl*>(host_ctl)->rbase; }
-int32_t serve_ctl_error(const void* host_ctl) { return static_cast<const Ctl*>(host_ctl)->error; }
 size_t serve_ctl_size() { return sizeof(Ctl); }
+
+kcore_status serve_rebase(ServeArena* A, int64_t nhi, int32_t d, void* stream) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nhi + kBlock - 1) / kBlock, (int64_t)A->num_cus * 16));
+  hipLaunchKernelGGL(k_rebase, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, A->stamp, A->gact, nhi, d,
+                     static_cast<Ctl*>(A->ctl));
+  KC_HIP(hipGetLastError());
+  return KCORE_OK;
+}
 
 }  // namespace kcore
 

@@ -182,7 +182,7 @@ struct kcore_server {
   kcore_status fatal = KCORE_OK;
   std::string fatal_msg;
   int64_t n_submitted = 0, n_completed = 0, n_cancelled = 0, n_rejected = 0, n_inflight = 0;
-  int64_t n_steps = 0, n_rounds = 0, bytes_used = 0, bytes_peak = 0;
+  int64_t n_steps = 0, n_rounds = 0, bytes_used = 0, bytes_peak = 0, n_rebases = 0;
   double t_first_submit = -1, t_last_done = 0;
   std::vector<double> latencies;
 
@@ -378,7 +378,6 @@ struct kcore_server {
       if ((s = admit()) != KCORE_OK) return s;
       std::this_thread::yield();
     }
-    if (serve_ctl_error(host_ctl)) return fail(KCORE_E_HIP, "tail round cap reached (internal error)");
     const int32_t r_new = serve_ctl_rbase(host_ctl);
     {
       std::lock_guard<std::mutex> lk(mu);
@@ -404,6 +403,16 @@ struct kcore_server {
       retiring.push_back(r);
       resident[i] = resident.back();
       resident.pop_back();
+    }
+    if (rbase > arena.tu.renorm) {
+      // round numbers stay far from the int32 range: renumber the live stamps and activity words
+      // (a multiple of 6 keeps every round's counter slot and list parity) before the next step or join
+      const int32_t d = (rbase - 64) / 6 * 6;
+      if ((s = serve_rebase(&arena, vspace.high_water(), d, cs)) != KCORE_OK) return s;
+      rbase -= d;
+      for (Request* r : resident) r->r_join -= d;
+      std::lock_guard<std::mutex> lk(mu);
+      ++n_rebases;
     }
     return KCORE_OK;
   }
@@ -639,6 +648,7 @@ kcore_status kcore_serve_stats(kcore_server* S, kcore_serve_report* out) {
   out->resident = S->n_inflight - out->queued;
   out->steps = S->n_steps;
   out->rounds = S->n_rounds;
+  out->rebases = S->n_rebases;
   out->bytes_budget = (int64_t)S->arena.bytes;
   out->bytes_peak = S->bytes_peak;
   if (!S->latencies.empty()) {

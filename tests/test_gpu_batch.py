@@ -1,5 +1,8 @@
 """Batched form: every graph's coreness in the batch equals the oracle, the same
 graph decomposed alone, and does not depend on the order of the batch."""
+import os
+import time
+
 import numpy as np
 import pytest
 
@@ -42,6 +45,25 @@ def test_batch_matches_oracle_and_plain():
         assert np.array_equal(alone.cpu().numpy(), got[v0:v1])
 
 
+def test_full_batch_workload_above_2_31_entries():
+    # the batched workload itself: 2048 graphs (seed 4), 4.08e9 entries, so the row offsets pass
+    # 2^31 and the automatic small-class grid grows to its largest size
+    t0 = time.time()
+    b = gg.batch(2048, seed=4, nmin=1000, nmax=1_000_000)
+    nnz = int(b.col_idx.size)
+    print(f"[batch] full workload generated in {time.time() - t0:.1f} s: N={int(b.graph_vtx_off[-1])} "
+          f"entries={nnz}", flush=True)
+    assert nnz > 2**31
+    st = kc().Stats()
+    got = run_batch(b, stats=st)
+    print(f"[batch] GPU done: rounds={st.rounds} tail={st.tail_rounds}", flush=True)
+    ref = oracle.coreness_batch(b.graph_vtx_off, b.row_ptr, b.col_idx, threads=min(16, os.cpu_count() or 1))
+    print(f"[batch] oracle done at {time.time() - t0:.1f} s", flush=True)
+    if not np.array_equal(got, ref):
+        bad = np.nonzero(got != ref)[0]
+        raise AssertionError(f"{bad.size} mismatches, first v={bad[0]} gpu={got[bad[0]]} ref={ref[bad[0]]}")
+
+
 def test_batch_order_does_not_matter():
     b = gg.batch(20, seed=9, nmin=500, nmax=20_000)
     got = run_batch(b)
@@ -73,7 +95,10 @@ def test_batch_edge_cases():
 
 @pytest.mark.parametrize("tuning", [dict(), dict(no_graph=1), dict(list_cap=1, tail_threshold=-1),
                                     dict(thread_max_deg=1, group_max_deg=1, wave_max_deg=1),
-                                    dict(activation=1, no_prune=1), dict(activation=2), dict(deferred=1)])
+                                    dict(activation=1, no_prune=1), dict(activation=2), dict(deferred=1),
+                                    dict(tail_order=1, tail_big=1, tail_threshold=1 << 30),
+                                    dict(tail_round_cap=2, tail_threshold=1 << 30),
+                                    dict(round_renorm=1024, rounds_per_poll=1)])
 def test_batch_tunings(tuning):
     b = gg.batch(16, seed=5, nmin=1000, nmax=30_000)
     got = run_batch(b, tuning=kc().Tuning(**tuning))

@@ -90,6 +90,79 @@ def test_large_cliques(k):
     assert (run_gpu(rp, ci) == k - 1).all()
 
 
+def clique_csr(k):
+    """K_k as a CSR built directly (k*(k-1) entries)."""
+    ids = np.broadcast_to(np.arange(k, dtype=np.int32), (k, k))
+    col = ids[~np.eye(k, dtype=bool)]
+    return np.arange(k + 1, dtype=np.int64) * (k - 1), np.ascontiguousarray(col)
+
+
+def dense_random_csr(n, seed):
+    """G(n, 1/2) as a CSR: each pair u < v joined with probability 1/2 (rows sorted)."""
+    rng = np.random.default_rng(seed)
+    a = rng.integers(0, 2, size=(n, n), dtype=np.uint8).astype(bool)
+    a = np.triu(a, 1)
+    a |= a.T
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(a.sum(axis=1), out=rp[1:])
+    ci = np.nonzero(a)[1].astype(np.int32)
+    return rp, ci
+
+
+def test_cores_above_the_histogram_bins():
+    # coreness above the 4096 LDS histogram bins: the one-pass search hands over to the
+    # multi-pass search over the global list (every value of a K_4500 lies above the bins)
+    rp, ci = clique_csr(4500)
+    assert_parity("K4500", rp, ci)
+    # a 4200-clique whose first ten vertices also carry 20,000 pendant leaves each (lists
+    # longer than the kept-values buffer, cores above the bins)
+    k, hubs, leaves = 4200, 10, 20_000
+    cr, cc = clique_csr(k)
+    src = [np.repeat(np.arange(k, dtype=np.int32), k - 1), np.repeat(np.arange(hubs, dtype=np.int32), leaves)]
+    dst = [cc, (k + np.arange(hubs * leaves)).astype(np.int32)]
+    g = gg.from_edges(k + hubs * leaves, np.concatenate(src), np.concatenate(dst))
+    assert_parity("K4200+pendant hubs", g.row_ptr, g.col_idx)
+    # dense G(12000, 1/2): degrees about 6000, cores above 4096 (pruned lists of thousands)
+    rp, ci = dense_random_csr(12_000, seed=17)
+    got = assert_parity("G(12000,1/2)", rp, ci)
+    assert got.min() > 4096
+
+
+def test_long_path_through_resumed_tails():
+    # a path needs about n/2 rounds (one vertex from each end per round); the tail hands its
+    # frontier back to the round launches every tail_round_cap rounds
+    n = 1_000_000
+    g = gg.from_edges(n, np.arange(n - 1), np.arange(1, n))
+    st = kc().Stats()
+    assert (run_gpu(g.row_ptr, g.col_idx, stats=st) == 1).all()
+    print(f"[parity] path 1e6: rounds={st.rounds} tail={st.tail_rounds} launches={st.launches}", flush=True)
+    assert st.rounds >= n // 2 - 2
+    n = 10_000
+    g = gg.from_edges(n, np.arange(n - 1), np.arange(1, n))
+    for extra in ({}, dict(tail_order=1), dict(tail_big=1)):
+        st = kc().Stats()
+        t = kc().Tuning(tail_round_cap=1000, **extra)
+        assert (run_gpu(g.row_ptr, g.col_idx, tuning=t, stats=st) == 1).all(), extra
+        assert st.tail_rounds >= 4000 and st.launches >= 5, (extra, st.tail_rounds, st.launches)
+    # a chain of cliques of growing size joined by single edges: long drop chains with several levels
+    sizes = [3 + (i % 7) for i in range(3000)]
+    n, edges = sg.onion(sizes)
+    rp, ci = sg.to_csr(n, edges)
+    for extra in ({}, dict(tail_order=1), dict(tail_order=1, tail_big=1, tail_threshold=1 << 20)):
+        t = kc().Tuning(tail_round_cap=7, **extra)
+        assert np.array_equal(run_gpu(rp, ci, tuning=t), oracle.coreness(rp, ci)), extra
+
+
+def test_timing_with_long_first_chunk():
+    # more rounds in the first chunk than the timing mode keeps events for: the chunk is clamped
+    kc_ = kc()
+    g = gg.workload("rmat16")
+    st = kc_.Stats()
+    got = run_gpu(g.row_ptr, g.col_idx, tuning=kc_.Tuning(timing=1, rounds_per_poll=100), stats=st)
+    assert np.array_equal(got, oracle.coreness(g.row_ptr, g.col_idx))
+    assert st.total_ms > 0
+
+
 def test_long_path_and_onion():
     n = 200_000
     g = gg.from_edges(n, np.arange(n - 1), np.arange(1, n))
@@ -174,6 +247,14 @@ TUNINGS = {
     "no_prune_one_sided": dict(no_prune=1, activation=1, list_cap=64),
     "relabel_always": dict(relabel=2),
     "relabel_always_no_tail": dict(relabel=2, tail_threshold=-1, list_cap=256),
+    "tail_lowest_first": dict(tail_order=1, tail_threshold=1 << 30),
+    "tail_lowest_first_default_threshold": dict(tail_order=1),
+    "tail_with_class3": dict(tail_big=1, tail_threshold=4096),
+    "tail_with_class3_lowest_first": dict(tail_big=1, tail_order=1, tail_threshold=1 << 30),
+    "tail_cap_3": dict(tail_round_cap=3, tail_threshold=1 << 30),
+    "tail_cap_1_lowest_first": dict(tail_round_cap=1, tail_order=1, tail_big=1, tail_threshold=1 << 30),
+    "renumber_often": dict(round_renorm=1024, rounds_per_poll=1),
+    "renumber_often_deferred": dict(round_renorm=1024, deferred=1, no_graph=1),
 }
 
 
@@ -264,12 +345,19 @@ def test_convergence_profile_reaches_the_coreness():
     assert rows[0]["active"] > 0 and rows[-1]["exact_share"] == 1.0
 
 
-def test_round_by_round_records():
+@pytest.mark.parametrize("name,tuning", [("rmat16", {}), ("rmat20", {}), ("rmat20", dict(tail_threshold=-1)),
+                                         ("rmat20", dict(deferred=1)), ("road_512", {})])
+def test_round_by_round_records(name, tuning):
     kc_ = kc()
-    g = gg.workload("rmat16")
+    g = gg.workload(name)
     dev = torch.device("cuda:0")
-    out, recs = kc_.decompose_rounds(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev))
+    rp, ci = torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev)
+    out, recs = kc_.decompose_rounds(rp, ci, tuning=kc_.Tuning(**tuning))
     assert np.array_equal(out.cpu().numpy(), oracle.coreness(g.row_ptr, g.col_idx))
     assert len(recs) >= 2 and [r["round"] for r in recs] == list(range(1, len(recs) + 1))
     assert recs[0]["vertex_updates"] == int((np.diff(g.row_ptr) >= 2).sum())  # the first round: degree >= 2
-    assert all(r["vertex_updates"] > 0 and r["ms"] > 0 for r in recs)
+    for r in recs:
+        assert r["vertex_updates"] > 0 and r["ms"] > 0, r
+        for key in ("vertex_updates", "edge_visits", "changes", "activations"):
+            assert r[key] >= 0, (key, r)
+        assert r["changes"] <= r["vertex_updates"] <= r["edge_visits"], r

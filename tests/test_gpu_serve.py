@@ -93,6 +93,31 @@ def test_matches_plain_decompose_on_batch_members():
     for g, out in zip(graphs, outs):
         plain = kc().decompose(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev))
         assert np.array_equal(plain.cpu().numpy(), out)
+        assert np.array_equal(oracle.coreness(g.row_ptr, g.col_idx), out)
+
+
+@pytest.mark.parametrize("tuning", [dict(round_renorm=1024), dict(round_renorm=1024, tail_round_cap=50),
+                                    dict(round_renorm=1024, tail_order=1, tail_big=1)])
+def test_round_numbers_renumbered_while_serving(tuning):
+    # long chains keep the server running thousands of rounds; with a low renumbering threshold the
+    # stamps and activity words are renumbered many times while graphs join and leave
+    graphs = []
+    for n in (20_000, 7_000, 30_000):
+        graphs.append(gg.from_edges(n, np.arange(n - 1), np.arange(1, n)))
+    graphs += [gg.chung_lu(50_000, 2.3, 12, seed=71), gg.lattice(120, 120, seed=72)]
+    sizes = [3 + (i % 9) for i in range(2000)]
+    n, edges = sg.onion(sizes)
+    graphs.append(gg.Graph(*sg.to_csr(n, edges)))
+    graphs = graphs * 2
+    refs = [oracle.coreness(g.row_ptr, g.col_idx) for g in graphs]
+    with kc().Server(hbm_budget_bytes=1 << 30, tuning=kc().Tuning(**tuning), rounds_per_step=8) as s:
+        rng = np.random.default_rng(9)
+        outs = run_all(s, graphs, gaps_s=rng.exponential(0.002, len(graphs)))
+        st = s.stats()
+    print(f"[serve] rebases={st['rebases']} rounds={st['rounds']} steps={st['steps']}", flush=True)
+    assert st["rebases"] >= 2
+    for g, out, ref in zip(graphs, outs, refs):
+        assert np.array_equal(out, ref)
 
 
 def test_budget_binds_admission():
