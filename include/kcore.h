@@ -179,6 +179,29 @@ kcore_status kcore_decompose_ex(int64_t n, const int64_t* row_ptr, const int32_t
 kcore_status kcore_decompose32_ex(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
                                   const kcore_tuning* tuning, kcore_stats* stats, void* stream);
 
+/*
+ * kcore_decompose_noalloc -- kcore_decompose for callers that cannot allocate
+ * (code that must not call hipMalloc, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, result and synchronisation as
+ * kcore_decompose, with default tuning.  The call allocates nothing: no device
+ * or pinned memory, no captured graph, no allocating library routine.  Its
+ * whole workspace (round stamps, frontier lists, pruned lists, control block)
+ * is one fixed device array of at most KCORE_NOALLOC_SCRATCH_BYTES bytes that
+ * the library's code object defines; every device the library runs on holds
+ * its own copy until the process ends.  Limits: n <= KCORE_NOALLOC_MAX_VERTICES
+ * and row_ptr[n] <= KCORE_NOALLOC_MAX_ENTRIES, else KCORE_E_TOO_LARGE (checked
+ * before any kernel runs; reading row_ptr[n] synchronises `stream`).
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (stamps stay below the next call's round numbers).  Calls on one
+ * device are serialised by the library; work that another caller enqueues
+ * into the same array by other means would race with it.
+ */
+#define KCORE_NOALLOC_MAX_VERTICES (1ll << 20)
+#define KCORE_NOALLOC_MAX_ENTRIES (1ll << 23)
+#define KCORE_NOALLOC_SCRATCH_BYTES (64ll << 20)
+kcore_status kcore_decompose_noalloc(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
+                                     void* stream);
+
 /* One round of a run recorded by kcore_decompose_rounds. */
 typedef struct kcore_round_record {
   int32_t round;           /* 1 = the first round (every vertex of degree >= 2) */

@@ -15,7 +15,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["decompose", "decompose_rounds", "decompose_batch", "autotune_batch", "tuning_cache_set", "tuning_cache_get", "Tuning",
+__all__ = ["decompose", "decompose_noalloc", "decompose_rounds", "decompose_batch", "autotune_batch", "tuning_cache_set", "tuning_cache_get", "Tuning",
            "Stats", "KcoreError", "Server", "ServeConfig", "Completion", "library_path", "load", "version"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -201,6 +201,8 @@ def load():
     lib.kcore_decompose32_ex.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats), vp]
     lib.kcore_decompose_ex.restype = i32
     lib.kcore_decompose_ex.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats), vp]
+    lib.kcore_decompose_noalloc.restype = i32
+    lib.kcore_decompose_noalloc.argtypes = [i64, vp, vp, vp, vp]
     lib.kcore_decompose_rounds.restype = i32
     lib.kcore_decompose_rounds.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(RoundRecord), i32,
                                            ctypes.POINTER(i32), vp]
@@ -293,6 +295,21 @@ def decompose(row_ptr, col_idx, out=None, tuning: Tuning | None = None, stats: S
         _check(lib.kcore_decompose_ex(n, row_ptr.data_ptr(), col_ptr, out.data_ptr(),
                                       ctypes.byref(tuning) if tuning is not None else None,
                                       ctypes.byref(stats) if stats is not None else None, st))
+    return out
+
+
+def decompose_noalloc(row_ptr, col_idx, out, stream=None):
+    """``kcore_decompose_noalloc``: like ``decompose`` (int64 row offsets, default tuning) into a caller-given
+    ``out``, with the library allocating nothing (its workspace is a fixed device array)."""
+    import torch
+    lib = load()
+    if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32 or not (row_ptr.is_cuda and col_idx.is_cuda):
+        raise TypeError("row_ptr must be an int64 and col_idx an int32 CUDA tensor")
+    n = row_ptr.numel() - 1
+    if out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError("out must be a contiguous int32 CUDA tensor of n elements")
+    col_ptr = col_idx.data_ptr() if col_idx.numel() else out.data_ptr()
+    _check(lib.kcore_decompose_noalloc(n, row_ptr.data_ptr(), col_ptr, out.data_ptr(), _stream_handle(stream)))
     return out
 
 

@@ -769,6 +769,123 @@ static kcore_status decompose_impl(int64_t n, const Off* row_ptr, const int32_t*
   return run_rounds<false, Off>(ws, n, nnz, row_ptr, col, out, tu, stats, st, rec);
 }
 
+// ------------------------------------------------------------------ no-allocation entry point
+// kcore_decompose_noalloc keeps its whole workspace in one device array of
+// fixed size, `scratch`, which the code object defines: every device the
+// library runs on holds its own copy from the first kernel launch until the
+// process ends, and the call itself allocates nothing (no hipMalloc, no
+// pinned host buffer, no captured graph).  Host code never passes the array's
+// name to a kernel: that name is a host-side stand-in, not a device address.
+// The device address comes from hipGetSymbolAddress, once per device, at the
+// first call on it, and is kept per device.
+constexpr int64_t kNoAllocMaxN = KCORE_NOALLOC_MAX_VERTICES;
+constexpr int64_t kNoAllocMaxNnz = KCORE_NOALLOC_MAX_ENTRIES;
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+// Layout: control block, validation word, then the per-vertex arrays (stamp,
+// class, two frontier lists, first-round list, pruned length, pruned threshold,
+// slack) and the pruned adjacency.
+constexpr size_t kScratchCtl = 0;
+constexpr size_t kScratchVerr = kScratchCtl + align256(sizeof(Ctl));
+constexpr size_t kScratchStamp = kScratchVerr + 256;
+constexpr size_t kScratchCls = kScratchStamp + align256(4 * kNoAllocMaxN);
+constexpr size_t kScratchList0 = kScratchCls + align256(kNoAllocMaxN);
+constexpr size_t kScratchList1 = kScratchList0 + align256(4 * kNoAllocMaxN);
+constexpr size_t kScratchSlist = kScratchList1 + align256(4 * kNoAllocMaxN);
+constexpr size_t kScratchPlen = kScratchSlist + align256(4 * kNoAllocMaxN);
+constexpr size_t kScratchPlow = kScratchPlen + align256(4 * kNoAllocMaxN);
+constexpr size_t kScratchSlack = kScratchPlow + align256(4 * kNoAllocMaxN);
+constexpr size_t kScratchPruned = kScratchSlack + align256(4 * kNoAllocMaxN);
+constexpr size_t kScratchBytes = kScratchPruned + align256(4 * kNoAllocMaxNnz);
+static_assert(kScratchBytes <= KCORE_NOALLOC_SCRATCH_BYTES, "scratch larger than the header states");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct NoAllocState {
+  unsigned char* dev = nullptr;  // device address of this device's scratch
+  int num_cus = 0;
+  int32_t epoch = 1;             // next round base (stamps of earlier calls are all below it)
+  Ctl host_ctl;                  // host copy of the control block (plain host memory)
+  int64_t host_word = 0;         // host copy of row_ptr[n] or of the validation word
+};
+static std::mutex g_noalloc_mu;
+static NoAllocState g_noalloc[64];
+
+// Device address of the scratch array on the current device (kept per device); the stamps start at 0.
+static kcore_status noalloc_setup(int dev, hipStream_t st) {
+  NoAllocState& S = g_noalloc[dev];
+  if (S.dev) return KCORE_OK;
+  void* ptr = nullptr;
+  KC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return fail(KCORE_E_HIP, "hipGetSymbolAddress(scratch) returned no address");
+  int cus = 0;
+  KC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  unsigned char* base = static_cast<unsigned char*>(ptr);
+  const int grid = (int)std::min<int64_t>((kNoAllocMaxN + kBlock - 1) / kBlock, (int64_t)cus * 16);
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, st, reinterpret_cast<int32_t*>(base + kScratchStamp),
+                     kNoAllocMaxN, 0);
+  KC_HIP(hipGetLastError());
+  S.dev = base;
+  S.num_cus = cus;
+  S.epoch = 1;
+  return KCORE_OK;
+}
+
+static kcore_status decompose_noalloc_impl(int64_t n, const int64_t* row_ptr, const int32_t* col, int32_t* out,
+                                           hipStream_t st) {
+  if (n < 0 || n > INT32_MAX) return fail(KCORE_E_INVALID, "n must be in [0, 2^31-1]");
+  if (n > kNoAllocMaxN)
+    return fail(KCORE_E_TOO_LARGE, "kcore_decompose_noalloc: n=" + std::to_string(n) + " exceeds " +
+                                       std::to_string(kNoAllocMaxN) + " vertices");
+  if (n == 0) return KCORE_OK;
+  if (!row_ptr || !col || !out) return fail(KCORE_E_INVALID, "null pointer argument");
+  int dev = 0;
+  KC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(KCORE_E_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  kcore_status s = noalloc_setup(dev, st);
+  if (s != KCORE_OK) return s;
+  NoAllocState& S = g_noalloc[dev];
+  S.host_word = -1;
+  KC_HIP(hipMemcpyAsync(&S.host_word, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  KC_HIP(hipStreamSynchronize(st));
+  const int64_t nnz = S.host_word;
+  if (nnz < 0) return fail(KCORE_E_INVALID, "row_ptr[n] is negative");
+  if (nnz > kNoAllocMaxNnz)
+    return fail(KCORE_E_TOO_LARGE, "kcore_decompose_noalloc: " + std::to_string(nnz) + " adjacency entries exceed " +
+                                       std::to_string(kNoAllocMaxNnz));
+  // A workspace view of the scratch array (registered nowhere; it owns nothing).
+  Workspace ws;
+  ws.device = dev;
+  ws.num_cus = S.num_cus;
+  ws.cap_n = kNoAllocMaxN;
+  ws.cap_nnz = kNoAllocMaxNnz;
+  ws.ctl = reinterpret_cast<Ctl*>(S.dev + kScratchCtl);
+  ws.verr = reinterpret_cast<int32_t*>(S.dev + kScratchVerr);
+  ws.stamp = reinterpret_cast<int32_t*>(S.dev + kScratchStamp);
+  ws.cls = S.dev + kScratchCls;
+  ws.lists[0] = reinterpret_cast<int32_t*>(S.dev + kScratchList0);
+  ws.lists[1] = reinterpret_cast<int32_t*>(S.dev + kScratchList1);
+  ws.slist = reinterpret_cast<int32_t*>(S.dev + kScratchSlist);
+  ws.plen = reinterpret_cast<int32_t*>(S.dev + kScratchPlen);
+  ws.plow = reinterpret_cast<int32_t*>(S.dev + kScratchPlow);
+  ws.slack = reinterpret_cast<int32_t*>(S.dev + kScratchSlack);
+  ws.pruned = reinterpret_cast<int32_t*>(S.dev + kScratchPruned);
+  ws.host_ctl = &S.host_ctl;
+  ws.host_verr = reinterpret_cast<int32_t*>(&S.host_word);
+  ws.epoch = S.epoch;
+  if (env_flag("KCORE_VALIDATE")) {
+    s = validate_csr<int64_t>(&ws, n, row_ptr, col, st);
+    if (s != KCORE_OK) return s;
+  }
+  Tuning tu = resolve_tuning(nullptr, S.num_cus);
+  tu.use_graph = 0;  // instantiating a graph allocates
+  tu.defer = 0;      // no deferred-check buffer: such neighbours are re-activated
+  settle_tuning(&tu, n, nnz, false);
+  s = run_rounds<false, int64_t>(&ws, n, nnz, row_ptr, col, out, tu, nullptr, st);
+  S.epoch = ws.epoch;
+  return s;
+}
+
 template <typename Off>
 static kcore_status validate_batch(Workspace* ws, int64_t n, const Off* row_ptr, const int32_t* col,
                                    hipStream_t st) {
@@ -1140,6 +1257,11 @@ kcore_status kcore_decompose_ex(int64_t n, const int64_t* row_ptr, const int32_t
 kcore_status kcore_decompose32_ex(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
                                   const kcore_tuning* tuning, kcore_stats* stats, void* stream) {
   return decompose_impl<int32_t>(n, row_ptr, col_idx, out_core, tuning, stats, (hipStream_t)stream);
+}
+
+kcore_status kcore_decompose_noalloc(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
+                                     void* stream) {
+  return decompose_noalloc_impl(n, row_ptr, col_idx, out_core, (hipStream_t)stream);
 }
 
 kcore_status kcore_decompose_rounds(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
