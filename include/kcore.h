@@ -125,6 +125,7 @@ typedef struct kcore_kernel_stats {
   int64_t activations;     /* vertices it put in a next frontier */
   int64_t prune_writes;    /* entries it wrote to pruned neighbour lists */
   int64_t full_scans;      /* recomputations that read the full neighbour list */
+  int64_t max_full_scan;   /* class-3 kernels: the longest full neighbour list one recomputation read */
   double ms;               /* summed launch durations (timing mode only: HIP events on the stream) */
 } kcore_kernel_stats;
 
@@ -202,6 +203,56 @@ kcore_status kcore_decompose32_ex(int64_t n, const int32_t* row_ptr, const int32
 kcore_status kcore_decompose_noalloc(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
                                      void* stream);
 
+/*
+ * kcore_update -- coreness after edge changes, from the coreness before them
+ * (core maintenance on a changing graph: the paper's future work on dynamic
+ * graphs, Sec. VI; the iteration of Sec. II-B restarted from a pointwise upper
+ * bound of the new coreness, which the monotone updates lower to exactly the
+ * new coreness, as from the degrees).
+ *   n, row_ptr, col_idx   DEVICE, the graph AFTER the changes, as for kcore_decompose.
+ *   prev_core             DEVICE int32[n]: the coreness of the graph before the changes
+ *                         (same vertex ids).  May alias out_core (update in place).
+ *   removed               DEVICE int32[2 * n_removed]: pairs {u, v} of the edges present before and
+ *                         absent now (each edge once, either orientation).
+ *   inserted              DEVICE int32[2 * n_inserted]: the edges absent before and present now.
+ *   out_core              DEVICE int32[n]: the coreness of the graph after the changes.
+ *   tuning, stats, stream as for kcore_decompose_ex (relabel and max_rounds are ignored).
+ * The result is exact when the graph before the changes is the graph after them
+ * with `inserted` removed and `removed` added back, and prev_core is its coreness;
+ * otherwise it is unspecified (but memory-safe for in-range ids).  Ids must lie
+ * in [0, n) (with KCORE_VALIDATE=1 the new CSR is checked, not the lists).
+ * Start: removals only lower coreness, so the old coreness bounds the new one
+ * and only the endpoints of removed edges are recomputed first; an insertion
+ * raises coreness by at most one, only on vertices connected to its endpoints
+ * through vertices of the smaller endpoint's coreness, so the vertices that
+ * reach an inserted endpoint (in the new graph) through vertices whose old
+ * coreness is at least the smallest old coreness of an inserted endpoint start
+ * from max(old, min(degree, old + n_inserted)) and are recomputed first.  Work
+ * therefore follows the extent of the change rather than the graph.
+ * Synchronises `stream` once per level of that search and as kcore_decompose does.
+ */
+kcore_status kcore_update(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* prev_core,
+                          int64_t n_removed, const int32_t* removed, int64_t n_inserted, const int32_t* inserted,
+                          int32_t* out_core, const kcore_tuning* tuning, kcore_stats* stats, void* stream);
+
+/*
+ * kcore_certify -- check a claimed coreness vector on the device, with no
+ * reference result: the local conditions Definition 1 (Sec. II) implies.
+ *   n, row_ptr, col_idx   DEVICE, the graph, as for kcore_decompose.
+ *   core                  DEVICE int32[n], the vector to check.
+ *   out_code              HOST: 0 when every condition holds; else, for the smallest vertex that fails
+ *                         one, the first condition it fails (4 only when no vertex fails 1-3):
+ *                         1 a core outside [0, degree]; 2 an isolated vertex with a nonzero core, or a
+ *                         vertex with neighbours and core 0; 3 a vertex v with fewer than core(v)
+ *                         neighbours of core >= core(v) (then {core >= k} does not induce minimum degree
+ *                         >= k); 4 k_max (k_max + 1) / 2 larger than the number of edges.
+ *   out_vertex            HOST: for codes 1-3 that vertex (-1 otherwise).
+ * Passing is necessary, not sufficient: maximality of the cores is not a local
+ * property (on K_4, the vector of all 2 passes).  Synchronises `stream`.
+ */
+kcore_status kcore_certify(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* core,
+                           int32_t* out_code, int64_t* out_vertex, void* stream);
+
 /* One round of a run recorded by kcore_decompose_rounds. */
 typedef struct kcore_round_record {
   int32_t round;           /* 1 = the first round (every vertex of degree >= 2) */
@@ -210,7 +261,9 @@ typedef struct kcore_round_record {
   int64_t edge_visits;     /* adjacency entries read by those recomputations */
   int64_t changes;         /* estimate decreases */
   int64_t activations;     /* vertices put in the next frontier */
+  int64_t max_full_scan;   /* the longest full neighbour list one class-3 recomputation read in this round */
   double ms;               /* duration of the round's kernels (HIP events on the stream) */
+  double big_ms;           /* of which the class-3 kernel */
 } kcore_round_record;
 
 /*

@@ -15,7 +15,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["decompose", "decompose_noalloc", "decompose_rounds", "decompose_batch", "autotune_batch", "tuning_cache_set", "tuning_cache_get", "Tuning",
+__all__ = ["decompose", "update", "certify", "decompose_noalloc", "decompose_rounds", "decompose_batch", "autotune_batch", "tuning_cache_set", "tuning_cache_get", "Tuning",
            "Stats", "KcoreError", "Server", "ServeConfig", "Completion", "library_path", "load", "version"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -82,6 +82,7 @@ class KernelStats(ctypes.Structure):
         ("activations", ctypes.c_int64),
         ("prune_writes", ctypes.c_int64),
         ("full_scans", ctypes.c_int64),
+        ("max_full_scan", ctypes.c_int64),
         ("ms", ctypes.c_double),
     ]
 
@@ -122,7 +123,9 @@ class RoundRecord(ctypes.Structure):
         ("edge_visits", ctypes.c_int64),
         ("changes", ctypes.c_int64),
         ("activations", ctypes.c_int64),
+        ("max_full_scan", ctypes.c_int64),
         ("ms", ctypes.c_double),
+        ("big_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -203,6 +206,11 @@ def load():
     lib.kcore_decompose_ex.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats), vp]
     lib.kcore_decompose_noalloc.restype = i32
     lib.kcore_decompose_noalloc.argtypes = [i64, vp, vp, vp, vp]
+    lib.kcore_certify.restype = i32
+    lib.kcore_certify.argtypes = [i64, vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i64), vp]
+    lib.kcore_update.restype = i32
+    lib.kcore_update.argtypes = [i64, vp, vp, vp, i64, vp, i64, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats),
+                                 vp]
     lib.kcore_decompose_rounds.restype = i32
     lib.kcore_decompose_rounds.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(RoundRecord), i32,
                                            ctypes.POINTER(i32), vp]
@@ -310,6 +318,66 @@ def decompose_noalloc(row_ptr, col_idx, out, stream=None):
         raise ValueError("out must be a contiguous int32 CUDA tensor of n elements")
     col_ptr = col_idx.data_ptr() if col_idx.numel() else out.data_ptr()
     _check(lib.kcore_decompose_noalloc(n, row_ptr.data_ptr(), col_ptr, out.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+CERTIFY_MESSAGES = {
+    0: "ok",
+    1: "core outside [0, degree]",
+    2: "isolated vertex with a nonzero core, or a vertex with neighbours and core 0",
+    3: "fewer than core(v) neighbours with core >= core(v)",
+    4: "kmax(kmax+1)/2 exceeds the number of edges",
+}
+
+
+def certify(row_ptr, col_idx, core, stream=None):
+    """``kcore_certify``: (code, vertex) of the local certificate of ``core`` on the device; code 0 = passes."""
+    import torch
+    lib = load()
+    if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32 or not (row_ptr.is_cuda and col_idx.is_cuda):
+        raise TypeError("row_ptr must be an int64 and col_idx an int32 CUDA tensor")
+    n = row_ptr.numel() - 1
+    if core.dtype != torch.int32 or core.numel() != n or not core.is_cuda or not core.is_contiguous():
+        raise ValueError("core must be a contiguous int32 CUDA tensor of n elements")
+    code, vertex = ctypes.c_int32(), ctypes.c_int64()
+    col_ptr = col_idx.data_ptr() if col_idx.numel() else core.data_ptr()
+    _check(lib.kcore_certify(n, row_ptr.data_ptr(), col_ptr, core.data_ptr(), ctypes.byref(code), ctypes.byref(vertex),
+                             _stream_handle(stream)))
+    return int(code.value), int(vertex.value)
+
+
+def update(row_ptr, col_idx, prev_core, removed=None, inserted=None, out=None, tuning: Tuning | None = None,
+           stats: Stats | None = None, stream=None):
+    """Coreness after edge changes (``kcore_update``).
+
+    row_ptr / col_idx: the graph after the changes (int64 / int32 CUDA tensors); prev_core: int32 CUDA
+    tensor [n], the coreness before; removed / inserted: int32 CUDA tensors of shape [k, 2] (or None),
+    the edges taken out and put in.  ``out`` may be ``prev_core`` itself.  Returns ``out``.
+    """
+    import torch
+    lib = load()
+    if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32 or not (row_ptr.is_cuda and col_idx.is_cuda):
+        raise TypeError("row_ptr must be an int64 and col_idx an int32 CUDA tensor")
+    n = row_ptr.numel() - 1
+    if prev_core.dtype != torch.int32 or prev_core.numel() != n or not prev_core.is_cuda or not prev_core.is_contiguous():
+        raise ValueError("prev_core must be a contiguous int32 CUDA tensor of n elements")
+    edges = []
+    for e, name in ((removed, "removed"), (inserted, "inserted")):
+        if e is None or e.numel() == 0:
+            edges.append((0, None))
+            continue
+        if e.dtype != torch.int32 or not e.is_cuda or not e.is_contiguous() or e.dim() != 2 or e.shape[1] != 2:
+            raise ValueError(f"{name} must be a contiguous int32 CUDA tensor of shape [k, 2]")
+        edges.append((e.shape[0], e.data_ptr()))
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+    elif out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError("out must be a contiguous int32 CUDA tensor of n elements")
+    col_ptr = col_idx.data_ptr() if col_idx.numel() else out.data_ptr()
+    _check(lib.kcore_update(n, row_ptr.data_ptr(), col_ptr, prev_core.data_ptr(), edges[0][0], edges[0][1],
+                            edges[1][0], edges[1][1], out.data_ptr(),
+                            ctypes.byref(tuning) if tuning is not None else None,
+                            ctypes.byref(stats) if stats is not None else None, _stream_handle(stream)))
     return out
 
 

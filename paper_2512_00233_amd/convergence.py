@@ -6,10 +6,11 @@ vertices is active in each round (Fig. 5).  This tool measures both for the
 GPU path on a graph resident in device memory: for r = 1, 2, ... it runs the
 decomposition stopped after r rounds (``kcore_tuning.max_rounds``; the tail is
 off so that every round is a separate launch), reads the estimates, and
-compares them with the final result of a full run.  Active and changed counts
-per round come from one run launched round by round.  Each stopped run is a
-separate asynchronous schedule, so the error rows come from different
-(equally valid) interleavings.
+compares them with a reference coreness supplied by the caller (the tests
+supply the CPU oracle's; without one, the final result of a full run is used).
+Active and changed counts per round come from one run launched round by round.
+Each stopped run is a separate asynchronous schedule, so the error rows come
+from different (equally valid) interleavings.
 
     python -m paper_2512_00233_amd.convergence --workload rmat24 [--max-rounds 80]
 """
@@ -21,18 +22,19 @@ import json
 import numpy as np
 
 
-def profile(row_ptr, col_idx, max_rounds: int = 200):
+def profile(row_ptr, col_idx, max_rounds: int = 200, reference=None):
     """Rows of (round, active vertices, changed vertices, mean |est - core|, max error, exact share).
 
     Active and changed counts come from one run recorded round by round
     (``kcore_decompose_rounds``); the errors after r rounds from a run stopped
-    there (``max_rounds = r``).
+    there (``max_rounds = r``), against ``reference`` (numpy int32 [n], the
+    coreness) when given, else against the final result of the recorded run.
     """
     import paper_2512_00233_amd as kc
     import torch
     n = row_ptr.numel() - 1
     core_t, recs = kc.decompose_rounds(row_ptr, col_idx, tuning=kc.Tuning(tail_threshold=-1))
-    core = core_t.cpu().numpy()
+    core = core_t.cpu().numpy() if reference is None else np.asarray(reference, dtype=np.int64)
     total = len(recs)
     rows = []
     for rec in recs[:max_rounds]:
@@ -43,6 +45,7 @@ def profile(row_ptr, col_idx, max_rounds: int = 200):
         if (err < 0).any():
             raise RuntimeError(f"round {r}: an estimate fell below the coreness")
         rows.append({"round": r, "active": rec["vertex_updates"], "changed": rec["changes"],
+                     "activations": rec["activations"], "edge_visits": rec["edge_visits"],
                      "active_share": rec["vertex_updates"] / max(n, 1), "ms": rec["ms"],
                      "mean_abs_err": float(err.mean()) if n else 0.0, "max_err": int(err.max()) if n else 0,
                      "exact_share": float((err == 0).mean()) if n else 1.0})

@@ -121,6 +121,9 @@ struct Ctl {
   int32_t resume;
   int32_t resume_round;
   int32_t resume_cnt[kClasses];
+  // longest full adjacency scan of the class-3 kernel: over the run by kernel, and in the current round
+  uint32_t maxscan_run[5];
+  uint32_t maxscan_round;
   // deferred same-kernel checks appended in the current round, one counter per
   // buffer region (a workgroup appends to region blockIdx.x % kDeferRegions)
   int32_t dcnt[128];

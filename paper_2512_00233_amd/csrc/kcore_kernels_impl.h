@@ -800,7 +800,7 @@ __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t
 // threshold L (they can never rise again), the list is compacted in place.
 template <int BLOCK, bool BATCH, typename Off>
 __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32_t u, bool dense, int32_t round,
-                                        LaneStats& st, int32_t* red, int32_t* hist, uint16_t* stash) {
+                                        LaneStats& st, int32_t* red, int32_t* hist, uint16_t* stash, bool track) {
   constexpr int R = kBigRegs;
   constexpr int CAPR = BLOCK * R;
   const int tid = threadIdx.x;
@@ -886,6 +886,10 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
     if (tid == 0) {
       st.v[ST_VISITS] += d;
       st.v[ST_FULL_SCANS] += 1;
+      if (track) {  // counted runs: the longest full scan, over the run and in this round
+        atomicMax(&a.ctl->maxscan_run[dense ? KI_BIG_FIRST : KI_BIG], (uint32_t)d);
+        atomicMax(&a.ctl->maxscan_round, (uint32_t)d);
+      }
     }
     if (d <= CAPR) {
       load(a.col, d, gb);
@@ -1141,13 +1145,14 @@ __device__ __forceinline__ void tail_select(const Args<Off>& a, Frontier& f, int
                                             int32_t* bins, int32_t* red) {
   static_assert(BLOCK == kTailBins, "one bin per thread");
   const int tid = threadIdx.x;
-  const int32_t w[kClasses] = {1, kGroupLanes, kWave, BLOCK};
+  constexpr int32_t w[kClasses] = {1, kGroupLanes, kWave, BLOCK};
   int64_t total = 0;
 #pragma unroll
   for (int k = 0; k < kClasses; ++k) total += (int64_t)f.n[k] * w[k];
   if (total <= BLOCK) return;
   bins[tid] = 0;
   __syncthreads();
+#pragma unroll
   for (int k = 0; k < kClasses; ++k)
     for (int32_t i = tid; i < f.n[k]; i += BLOCK)
       atomicAdd(&bins[min(est_val(a.est[f.list[f.b[k] + i]]), kTailBins - 1)], w[k]);
@@ -1172,6 +1177,7 @@ __device__ __forceinline__ void tail_select(const Args<Off>& a, Frontier& f, int
   const int32_t tau = bin >= kTailBins - 1 ? INT32_MAX : bin;
   int32_t* next = list_of(a, r + 1);
   const int lane = lane_id();
+#pragma unroll
   for (int k = 0; k < kClasses; ++k) {
     int32_t kept = 0;
     for (int32_t j0 = 0; j0 < f.n[k]; j0 += BLOCK) {
@@ -1230,8 +1236,9 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
     if (f.n[0] + f.n[1] + f.n[2] + f.n[3] == 0) break;
     if (t >= a.tail_cap) {
       // the frontier of round r (stamps r, in the lists of round r) goes back to the round launches
-      if (tid < kClasses) ctl->resume_cnt[tid] = f.n[tid];
       if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < kClasses; ++k) ctl->resume_cnt[k] = f.n[k];
         ctl->resume_round = r;
         ctl->resume = 1;
       }
@@ -1427,6 +1434,7 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
   const int32_t round = ctl->rbase + slot;
   // this round's deferred checks start empty (the previous round's were consumed by its k_defer)
   if (!SEED && blockIdx.x == 0 && threadIdx.x < kDeferRegions) ctl->dcnt[threadIdx.x] = 0;
+  if (!SEED && blockIdx.x == 0 && threadIdx.x == 0) ctl->maxscan_round = 0;
   if (!SEED && ctl->overflow[round % 3][0] == 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int64_t n = a.served ? (int64_t)ctl->nhi : a.n;  // served graphs: the range of the live slots
@@ -1571,7 +1579,7 @@ __global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot,
   }
   for (int32_t i = blockIdx.x; i < f.n[3]; i += gridDim.x) {
     const int32_t u = f.list[f.b[3] + i];
-    upd_big<BLOCK, BATCH>(a, s, u, FIRST, round, st, red, hist, stash);
+    upd_big<BLOCK, BATCH>(a, s, u, FIRST, round, st, red, hist, stash, collect_stats != 0);
     if (FIRST && kBigFirst) {
       // every class-3 vertex is in the second round's frontier
       int32_t self[1] = {u};
@@ -1582,6 +1590,43 @@ __global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot,
     }
   }
   if (collect_stats) flush_stats<BLOCK>(ctl, FIRST ? KI_BIG_FIRST : KI_BIG, st, red64);
+}
+
+// Certificate of a claimed coreness vector, a check that needs no reference
+// result (the local conditions that Definition 1 implies): code 1 when a core
+// lies outside [0, degree], 2 when an isolated vertex has a nonzero core or a
+// vertex with neighbours has core 0, 3 when a vertex has fewer than core(v)
+// neighbours of core >= core(v) (then {core >= k} would not induce minimum
+// degree >= k).  The smallest failing vertex, with the first condition it
+// fails, is kept as one 64-bit word (vertex << 32 | code) by atomicMin; the largest core goes to
+// kmax for the host's check k_max (k_max + 1) / 2 <= m.  One wavefront per
+// vertex counts its supporting neighbours.  Maximality (no larger vector
+// passes) cannot be checked locally.
+template <typename Off>
+__global__ __launch_bounds__(256) void k_certify(int64_t n, const Off* row_ptr, const int32_t* col,
+                                                 const int32_t* core, unsigned long long* worst, int32_t* kmax) {
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+  int32_t km = 0;
+  for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; v < n; v += nw) {
+    const Off b = row_ptr[v], e = row_ptr[v + 1];
+    const int64_t d = (int64_t)(e - b);
+    const int32_t c = core[v];
+    km = max(km, c);
+    int code = 0;
+    if (c < 0 || c > d) code = 1;
+    else if ((d == 0) != (c == 0)) code = 2;
+    else if (c > 0) {
+      int64_t sup = 0;
+      for (Off j = b + lane; j < e; j += kWave) sup += core[col[j]] >= c;
+      sup = wave_sum(sup);
+      if (sup < c) code = 3;
+    }
+    if (code && lane == 0) atomicMin(worst, ((unsigned long long)v << 32) | (unsigned long long)code);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) km = max(km, __shfl_xor(km, o));
+  if (lane == 0 && km > 0) atomicMax(kmax, km);
 }
 
 // Precondition check (only when requested): ids in range, no self-loops,
@@ -1744,6 +1789,143 @@ __global__ void k_serve_reset(Ctl* ctl, int32_t r0) {
   for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / sizeof(int32_t)); i += blockDim.x) p[i] = 0;
   __syncthreads();
   if (threadIdx.x == 0) ctl->rbase = r0;
+}
+
+// ------------------------------------------------------------------ core maintenance after edge changes
+// The coreness c_old of a graph is known; edges D are removed and edges I
+// inserted (the paper's future work on dynamic graphs, Sec. VI).  The run
+// restarts the same iteration from a pointwise upper bound x of the new
+// coreness c_new, with a frontier that holds every vertex whose bound may
+// exceed the h-index of its neighbours' bounds:
+//  * removals only lower coreness, so x = c_old bounds every vertex; only the
+//    endpoints of D have a new neighbourhood;
+//  * one insertion raises coreness by at most 1, and only on vertices whose
+//    coreness equals K = min(c(u), c(v)) and that reach u or v through such
+//    vertices.  Over the batch, let T = min over I of min(c_old(u), c_old(v)).
+//    Coreness is monotone in the edge set, so a vertex w that rises also rises
+//    when only I is added, which needs c_old(w) >= T; and the component of w in
+//    the new (c_old(w)+1)-core holds an inserted edge (otherwise it was a core
+//    of the old graph) and only vertices of old coreness >= T (each either
+//    rose, or kept a coreness above c_old(w)).  So w reaches an endpoint of I
+//    in the new graph through vertices of old coreness >= T.  On the vertices
+//    so reached (the set A, found by a search from the endpoints)
+//    x = max(c_old, min(degree, c_old + |I|)); elsewhere x = c_old;
+//  * x never falls below c_old at the start (so no neighbour loses support
+//    unannounced), except on vertices left with degree <= 1, whose coreness is
+//    then known (0 or 1): they take it, and their neighbour joins the frontier.
+// Every other vertex keeps its neighbourhood and sees neighbour bounds >= c_old,
+// so its own bound is at most their h-index.  The slack of every vertex starts
+// at 0, so the first loss of support at its level activates it.
+
+// Flags (bit 0: endpoint of a removed edge, bit 1: in A) and the smallest old
+// coreness over the inserted edges' endpoints.
+__global__ __launch_bounds__(256) void k_upd_edges(const int32_t* del, int64_t nd, const int32_t* ins, int64_t ni,
+                                                   const int32_t* prev, int32_t* flag, int32_t* kmin) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int32_t m = INT32_MAX;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nd + ni; i += stride) {
+    if (i < nd) {
+      atomicOr(&flag[del[2 * i]], 1);
+      atomicOr(&flag[del[2 * i + 1]], 1);
+    } else {
+      const int64_t j = i - nd;
+      m = min(m, min(prev[ins[2 * j]], prev[ins[2 * j + 1]]));
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = min(m, __shfl_xor(m, o));
+  if (lane_id() == 0 && m != INT32_MAX) atomicMin(kmin, m);
+}
+
+// The search for A starts from the endpoints of the inserted edges.
+__global__ __launch_bounds__(256) void k_upd_bfs_start(const int32_t* ins, int64_t ni, int32_t* flag, int32_t* queue,
+                                                       int32_t* qcnt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * ni; i += stride) {
+    const int32_t w = ins[i];
+    if ((atomicOr(&flag[w], 2) & 2) == 0) queue[atomicAdd(qcnt, 1)] = w;
+  }
+}
+
+// One level of the search: one wavefront per queued vertex adds its neighbours
+// whose old coreness is at least T and that are not in A yet.
+template <typename Off>
+__global__ __launch_bounds__(256) void k_upd_bfs_level(const Off* row_ptr, const int32_t* col, const int32_t* prev,
+                                                       int32_t T, int32_t* flag, const int32_t* in_q,
+                                                       const int32_t* in_cnt, int32_t* out_q, int32_t* out_cnt) {
+  const int lane = lane_id();
+  const int64_t nq = *in_cnt;
+  const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < nq; q += nw) {
+    const int32_t u = in_q[q];
+    const Off b = row_ptr[u], e = row_ptr[u + 1];
+    for (Off j0 = b; j0 < e; j0 += kWave) {
+      const Off j = j0 + lane;
+      bool add = false;
+      int32_t w = 0;
+      if (j < e) {
+        w = col[j];
+        add = prev[w] >= T && (atomicOr(&flag[w], 2) & 2) == 0;
+      }
+      const uint64_t m = ballot(add);
+      if (!m) continue;
+      int32_t base = 0;
+      if (lane == 0) base = atomicAdd(out_cnt, popc(m));
+      base = __shfl(base, 0);
+      if (add) out_q[base + lanes_below(m)] = w;
+    }
+  }
+}
+
+// Start of an update run: estimates from the bounds above, classes and class
+// populations from the new degrees, no pruned lists, slack 0, and the round
+// stamp r on every frontier vertex (endpoints of removed edges, A, neighbours
+// of vertices left with degree 1); round r then builds its lists from the
+// stamps (a compaction round) as a later round.
+template <typename Off>
+__global__ __launch_bounds__(256) void k_upd_init(Args<Off> a, const int32_t* prev, const int32_t* flag, int64_t ni,
+                                                  int32_t r, int32_t t0, int32_t t1, int32_t t2) {
+  __shared__ uint32_t part[kClasses][256 / kWave];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctl->overflow[r % 3][0] = 1;
+    a.ctl->rbase = r;
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint32_t p[kClasses] = {0, 0, 0, 0};
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
+    const Off beg = a.row_ptr[v];
+    const int32_t d = (int32_t)(a.row_ptr[v + 1] - beg);
+    const int32_t c = prev[v];
+    const int32_t f = flag[v];
+    int64_t x = c;
+    if (f & 2) x = max((int64_t)c, min((int64_t)d, (int64_t)c + ni));
+    bool seed = f != 0;
+    if (d <= 1 && x > d) {
+      x = d;  // the coreness of a vertex of degree 0 or 1 is its degree
+      if (d == 1) a.stamp[a.col[beg]] = r;  // its neighbour lost support it had counted
+    }
+    if (d <= 1) seed = false;
+    const uint8_t cl = d <= 1 ? kClasses : (d <= t0 ? 0 : (d <= t1 ? 1 : (d <= t2 ? 2 : 3)));
+    a.est[v] = est_enc((int32_t)min(x, (int64_t)kEstMax), cl);
+    if (cl == 2 || cl == 3) a.plen[v] = 0;
+    a.cls[v] = cl;
+    a.slack[v] = 0;
+    if (seed) a.stamp[v] = r;
+#pragma unroll
+    for (int k = 0; k < kClasses; ++k) p[k] += cl == k;
+  }
+  const int wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < kClasses; ++k) {
+    const uint32_t w = wave_sum(p[k]);
+    if (lane_id() == 0) part[k][wave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < kClasses) {
+    uint32_t t = 0;
+    for (int w = 0; w < 256 / kWave; ++w) t += part[threadIdx.x][w];
+    if (t) atomicAdd(&a.ctl->pop[threadIdx.x], (int32_t)t);
+  }
 }
 
 // ------------------------------------------------------------------ degree relabelling

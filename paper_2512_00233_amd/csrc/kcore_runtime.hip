@@ -56,6 +56,10 @@ struct Workspace {
   Ctl* host_ctl = nullptr;      // pinned
   int32_t* verr = nullptr;      // validation result (device)
   int32_t* host_verr = nullptr;  // pinned
+  int32_t* aux = nullptr;       // update runs: smallest old coreness of inserted endpoints, search counters (device)
+  int32_t* host_aux = nullptr;  // pinned
+  int32_t* cert = nullptr;      // certificate: worst (code << 32 | vertex) as two words, then the largest core
+  int32_t* host_cert = nullptr; // pinned
   int64_t* host_nnz = nullptr;   // pinned
   int32_t epoch = 1;
   // degree relabelling (single-graph calls on skewed graphs)
@@ -142,6 +146,10 @@ static kcore_status get_workspace(Workspace** out) {
     KC_HIP(hipMalloc(&ws->verr, sizeof(int32_t)));
     KC_HIP(hipHostMalloc(&ws->host_verr, sizeof(int32_t), hipHostMallocDefault));
     KC_HIP(hipHostMalloc(&ws->host_nnz, sizeof(int64_t), hipHostMallocDefault));
+    KC_HIP(hipMalloc(&ws->aux, 4 * sizeof(int32_t)));
+    KC_HIP(hipHostMalloc(&ws->host_aux, 4 * sizeof(int32_t), hipHostMallocDefault));
+    KC_HIP(hipMalloc(&ws->cert, 4 * sizeof(int32_t)));
+    KC_HIP(hipHostMalloc(&ws->host_cert, 4 * sizeof(int32_t), hipHostMallocDefault));
     g_ws[dev] = ws;
   }
   *out = g_ws[dev];
@@ -431,12 +439,22 @@ static float elapsed(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
+// Start of an update run (kcore_update): the old coreness, the per-vertex
+// flags of the edge changes and the number of inserted edges.
+struct UpdateStart {
+  const int32_t* prev;
+  const int32_t* flag;
+  int64_t ni;
+};
+
 // Every vertex of every graph (one graph: vbase unused) to its fixpoint.
 // row_ptr holds global edge offsets; with BATCH, col holds graph-local ids.
+// With upd, the run starts from the bounds of an update instead of the degrees,
+// and its first round is an ordinary later round over the update's frontier.
 template <bool BATCH, typename Off>
 static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off* row_ptr, const int32_t* col,
                                int32_t* out, const Tuning& tu, kcore_stats* stats, hipStream_t st,
-                               std::vector<kcore_round_record>* rec = nullptr) {
+                               std::vector<kcore_round_record>* rec = nullptr, const UpdateStart* upd = nullptr) {
   const int init_grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16);
   const int cgrid = compact_grid(n, ws->num_cus);
   if (ws->epoch > (1 << 29)) {
@@ -485,15 +503,22 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   hipEvent_t* ev = timing ? ws->events.data() : nullptr;
   if (timing) KC_HIP(hipEventRecord(ev[0], st));
   hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, st, ws->ctl);
-  hipLaunchKernelGGL(k_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, r0, tu.t0, tu.t1, tu.t2);
-  hipLaunchKernelGGL((k_compact<true, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, 0);
-  launch_updates<true, BATCH, Off>(a, tu, 0, collect, st, timing ? ev + 1 : nullptr);
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, ws->ctl, 1);
+  if (upd) {
+    hipLaunchKernelGGL(k_upd_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, upd->prev, upd->flag, upd->ni,
+                       r0 + 1, tu.t0, tu.t1, tu.t2);
+    if (timing)
+      for (int i = 1; i <= 4; ++i) KC_HIP(hipEventRecord(ev[i], st));
+  } else {
+    hipLaunchKernelGGL(k_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, r0, tu.t0, tu.t1, tu.t2);
+    hipLaunchKernelGGL((k_compact<true, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, 0);
+    launch_updates<true, BATCH, Off>(a, tu, 0, collect, st, timing ? ev + 1 : nullptr);
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, ws->ctl, 1);
+  }
   KC_HIP(hipGetLastError());
   unsigned long long prev[KI_COUNT][kLaneStats];
   std::memset(prev, 0, sizeof(prev));
   unsigned long long prev_tail = 0;
-  auto trace_line = [&](const Ctl& h, int32_t r, const char* what, float ms) {
+  auto trace_line = [&](const Ctl& h, int32_t r, const char* what, float ms, float big_ms) {
     unsigned long long d[2][kLaneStats];  // [0]: class-3 kernels and deferred checks, [1]: classes 0..2
     std::memset(d, 0, sizeof(d));
     for (int k = 0; k < KI_COUNT; ++k)
@@ -511,17 +536,20 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
       x.edge_visits = (int64_t)(d[0][ST_VISITS] + d[1][ST_VISITS]);
       x.changes = (int64_t)(d[0][ST_CHANGES] + d[1][ST_CHANGES]);
       x.activations = (int64_t)(d[0][ST_ACTIVATIONS] + d[1][ST_ACTIVATIONS]);
+      x.max_full_scan = (int64_t)h.maxscan_round;
       x.ms = ms;
+      x.big_ms = big_ms;
       rec->push_back(x);
     }
     prev_tail = h.stats[ST_TAIL_ROUNDS];
     if (!trace_env) return;
     std::fprintf(stderr, "[kcore-trace] %s round=%d front=%d/%d/%d/%d dense=%d | big upd=%llu vis=%llu chg=%llu "
-                 "act=%llu full=%llu | small upd=%llu vis=%llu chg=%llu act=%llu full=%llu | tail=%llu ms=%.3f\n",
+                 "act=%llu full=%llu maxscan=%u big_ms=%.3f | small upd=%llu vis=%llu chg=%llu act=%llu full=%llu | "
+                 "tail=%llu ms=%.3f\n",
                  what, r - r0, h.cnt[r % 3][0], h.cnt[r % 3][1], h.cnt[r % 3][2], h.cnt[r % 3][3],
                  h.overflow[r % 3][0], d[0][ST_UPDATES], d[0][ST_VISITS], d[0][ST_CHANGES], d[0][ST_ACTIVATIONS],
-                 d[0][ST_FULL_SCANS], d[1][ST_UPDATES], d[1][ST_VISITS], d[1][ST_CHANGES], d[1][ST_ACTIVATIONS],
-                 d[1][ST_FULL_SCANS], h.stats[ST_TAIL_ROUNDS], ms);
+                 d[0][ST_FULL_SCANS], h.maxscan_round, big_ms, d[1][ST_UPDATES], d[1][ST_VISITS], d[1][ST_CHANGES],
+                 d[1][ST_ACTIVATIONS], d[1][ST_FULL_SCANS], h.stats[ST_TAIL_ROUNDS], ms);
   };
   if (timing) {
     KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -533,9 +561,10 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
       std::fprintf(stderr, "[kcore-trace] n=%lld nnz=%lld pop=%d/%d/%d/%d init_ms=%.3f\n", (long long)n,
                    (long long)nnz, ws->host_ctl->pop[0], ws->host_ctl->pop[1], ws->host_ctl->pop[2],
                    ws->host_ctl->pop[3], init_ms);
-    if (trace) trace_line(*ws->host_ctl, r0 + 1, "first", (float)(kms[0] + kms[1]));
+    if (trace && !upd) trace_line(*ws->host_ctl, r0 + 1, "first", (float)(kms[0] + kms[1]), (float)kms[0]);
   }
-  int64_t launches = 1;
+  const int64_t first_launches = upd ? 0 : 1;  // the first (all-vertex) round
+  int64_t launches = first_launches;
   int K = trace ? 1 : tu.poll;
   int32_t r = r0 + 1;
   int64_t rounds_done = 1;  // round numbers, across renumberings
@@ -569,7 +598,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
         kms[KCORE_K_BIG] += kBigFirst ? elapsed(e[1], e[2]) : elapsed(e[2], e[3]);
         kms[KCORE_K_ROUND] += kBigFirst ? elapsed(e[2], e[3]) : elapsed(e[1], e[2]);
         kms[KCORE_K_DEFER] += elapsed(e[3], e[4]);
-        if (trace) trace_line(h, r - 1, "", elapsed(e[0], e[4]));
+        if (trace) trace_line(h, r - 1, "", elapsed(e[0], e[4]), kBigFirst ? elapsed(e[1], e[2]) : elapsed(e[2], e[3]));
       }
     }
     const int32_t* c = h.cnt[r % 3];
@@ -606,7 +635,8 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     stats->dense_rounds = (int64_t)hc.stats[ST_DENSE_ROUNDS];
     stats->init_ms = init_ms;
     const bool defer_on = a.defer && !a.one_sided;
-    const int64_t kl[KCORE_K_COUNT] = {1, 1, launches - 1, launches - 1, launches - 1, defer_on ? launches - 1 : 0};
+    const int64_t later = launches - first_launches;
+    const int64_t kl[KCORE_K_COUNT] = {first_launches, first_launches, later, later, later, defer_on ? later : 0};
     // counters by public kernel index (the compaction kernel has none)
     const int kid[KCORE_K_COUNT] = {KI_BIG_FIRST, KI_ROUND_FIRST, KI_BIG, KI_ROUND, -1, KI_DEFER};
     for (int k = 0; k < KCORE_K_COUNT; ++k) {
@@ -620,6 +650,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
         o.activations = (int64_t)kstat(hc, kid[k], ST_ACTIVATIONS);
         o.prune_writes = (int64_t)kstat(hc, kid[k], ST_PRUNE_WRITES);
         o.full_scans = (int64_t)kstat(hc, kid[k], ST_FULL_SCANS);
+        o.max_full_scan = (int64_t)hc.maxscan_run[kid[k]];
         stats->vertex_updates += o.vertex_updates;
         stats->edge_visits += o.edge_visits;
         stats->changes += o.changes;
@@ -884,6 +915,114 @@ static kcore_status decompose_noalloc_impl(int64_t n, const int64_t* row_ptr, co
   s = run_rounds<false, int64_t>(&ws, n, nnz, row_ptr, col, out, tu, nullptr, st);
   S.epoch = ws.epoch;
   return s;
+}
+
+// ------------------------------------------------------------------ core maintenance (kcore_update)
+template <typename Off>
+static kcore_status update_impl(int64_t n, const Off* row_ptr, const int32_t* col, const int32_t* prev, int64_t nd,
+                                const int32_t* del, int64_t ni, const int32_t* ins, int32_t* out,
+                                const kcore_tuning* tuning, kcore_stats* stats, hipStream_t st) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (n < 0 || n > INT32_MAX) return fail(KCORE_E_INVALID, "n must be in [0, 2^31-1]");
+  if (nd < 0 || ni < 0) return fail(KCORE_E_INVALID, "edge counts must be >= 0");
+  if (n == 0) return KCORE_OK;
+  if (!row_ptr || !col || !prev || !out || (nd > 0 && !del) || (ni > 0 && !ins))
+    return fail(KCORE_E_INVALID, "null pointer argument");
+  Workspace* ws = nullptr;
+  kcore_status s = get_workspace(&ws);
+  if (s != KCORE_OK) return s;
+  std::lock_guard<std::mutex> lk(ws->mu);
+  *ws->host_nnz = 0;
+  KC_HIP(hipMemcpyAsync(ws->host_nnz, row_ptr + n, sizeof(Off), hipMemcpyDeviceToHost, st));
+  KC_HIP(hipStreamSynchronize(st));
+  const int64_t nnz = sizeof(Off) == 8 ? *ws->host_nnz : (int64_t)*(const int32_t*)ws->host_nnz;
+  if (nnz < 0) return fail(KCORE_E_INVALID, "row_ptr[n] is negative");
+  s = ensure_capacity(ws, n, nnz, false, st);
+  if (s != KCORE_OK) return s;
+  if (env_flag("KCORE_VALIDATE")) {
+    s = validate_csr<Off>(ws, n, row_ptr, col, st);
+    if (s != KCORE_OK) return s;
+  }
+  Tuning tu = resolve_tuning(tuning, ws->num_cus);
+  settle_tuning(&tu, n, nnz, false);
+  tu.max_rounds = 0;
+  // the flags live in the pruned-threshold array until the run starts (no pruned list exists then)
+  int32_t* flag = ws->plow;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16));
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, st, flag, n, 0);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, ws->aux, (int64_t)1, INT32_MAX);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, ws->aux + 1, (int64_t)3, 0);
+  if (nd + ni > 0) {
+    const int egrid = (int)std::max<int64_t>(1, std::min<int64_t>((nd + ni + kBlock - 1) / kBlock,
+                                                                    (int64_t)ws->num_cus * 16));
+    hipLaunchKernelGGL(k_upd_edges, dim3(egrid), dim3(kBlock), 0, st, del, nd, ins, ni, prev, flag, ws->aux);
+  }
+  KC_HIP(hipGetLastError());
+  if (ni > 0) {
+    KC_HIP(hipMemcpyAsync(ws->host_aux, ws->aux, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    KC_HIP(hipStreamSynchronize(st));
+    const int64_t T = ws->host_aux[0];
+    // breadth-first search from the inserted endpoints through vertices of old coreness >= T;
+    // the frontier lists serve as the search queues (each vertex enters one at most once)
+    const int sgrid = (int)std::max<int64_t>(1, std::min<int64_t>((2 * ni + kBlock - 1) / kBlock,
+                                                                   (int64_t)ws->num_cus * 16));
+    hipLaunchKernelGGL(k_upd_bfs_start, dim3(sgrid), dim3(kBlock), 0, st, ins, ni, flag, ws->lists[0], ws->aux + 1);
+    KC_HIP(hipGetLastError());
+    for (int level = 0;; ++level) {
+      int32_t* cnt_in = ws->aux + 1 + (level & 1);
+      int32_t* cnt_out = ws->aux + 1 + ((level + 1) & 1);
+      KC_HIP(hipMemcpyAsync(ws->host_aux + 1, cnt_in, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      KC_HIP(hipStreamSynchronize(st));
+      const int64_t nq = ws->host_aux[1];
+      if (nq == 0) break;
+      hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, cnt_out, (int64_t)1, 0);
+      const int lgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nq * kWave + kBlock - 1) / kBlock,
+                                                                     (int64_t)ws->num_cus * 16));
+      hipLaunchKernelGGL(k_upd_bfs_level<Off>, dim3(lgrid), dim3(kBlock), 0, st, row_ptr, col, prev, (int32_t)T,
+                         flag, ws->lists[level & 1], cnt_in, ws->lists[(level + 1) & 1], cnt_out);
+      KC_HIP(hipGetLastError());
+    }
+  }
+  const UpdateStart upd{prev, flag, ni};
+  return run_rounds<false, Off>(ws, n, nnz, row_ptr, col, out, tu, stats, st, nullptr, &upd);
+}
+
+// ------------------------------------------------------------------ certificate (kcore_certify)
+template <typename Off>
+static kcore_status certify_impl(int64_t n, const Off* row_ptr, const int32_t* col, const int32_t* core,
+                                 int32_t* out_code, int64_t* out_vertex, hipStream_t st) {
+  if (!out_code || !out_vertex) return fail(KCORE_E_INVALID, "null result pointer");
+  *out_code = 0;
+  *out_vertex = -1;
+  if (n < 0 || n > INT32_MAX) return fail(KCORE_E_INVALID, "n must be in [0, 2^31-1]");
+  if (n == 0) return KCORE_OK;
+  if (!row_ptr || !col || !core) return fail(KCORE_E_INVALID, "null pointer argument");
+  Workspace* ws = nullptr;
+  kcore_status s = get_workspace(&ws);
+  if (s != KCORE_OK) return s;
+  std::lock_guard<std::mutex> lk(ws->mu);
+  *ws->host_nnz = 0;
+  KC_HIP(hipMemcpyAsync(ws->host_nnz, row_ptr + n, sizeof(Off), hipMemcpyDeviceToHost, st));
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, ws->cert, (int64_t)2, (int32_t)-1);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, ws->cert + 2, (int64_t)2, 0);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n * kWave + kBlock - 1) / kBlock,
+                                                                (int64_t)ws->num_cus * 32));
+  hipLaunchKernelGGL(k_certify<Off>, dim3(grid), dim3(kBlock), 0, st, n, row_ptr, col, core,
+                     reinterpret_cast<unsigned long long*>(ws->cert), ws->cert + 2);
+  KC_HIP(hipGetLastError());
+  KC_HIP(hipMemcpyAsync(ws->host_cert, ws->cert, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  KC_HIP(hipStreamSynchronize(st));
+  const int64_t nnz = sizeof(Off) == 8 ? *ws->host_nnz : (int64_t)*(const int32_t*)ws->host_nnz;
+  unsigned long long w;
+  std::memcpy(&w, ws->host_cert, sizeof(w));
+  if (w != ~0ull) {
+    *out_vertex = (int64_t)(w >> 32);
+    *out_code = (int32_t)(w & 0xffffffffull);
+    return KCORE_OK;
+  }
+  const int64_t km = ws->host_cert[2];
+  if (km * (km + 1) / 2 > nnz / 2) *out_code = 4;
+  return KCORE_OK;
 }
 
 template <typename Off>
@@ -1262,6 +1401,18 @@ kcore_status kcore_decompose32_ex(int64_t n, const int32_t* row_ptr, const int32
 kcore_status kcore_decompose_noalloc(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,
                                      void* stream) {
   return decompose_noalloc_impl(n, row_ptr, col_idx, out_core, (hipStream_t)stream);
+}
+
+kcore_status kcore_update(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* prev_core,
+                          int64_t n_removed, const int32_t* removed, int64_t n_inserted, const int32_t* inserted,
+                          int32_t* out_core, const kcore_tuning* tuning, kcore_stats* stats, void* stream) {
+  return update_impl<int64_t>(n, row_ptr, col_idx, prev_core, n_removed, removed, n_inserted, inserted, out_core,
+                              tuning, stats, (hipStream_t)stream);
+}
+
+kcore_status kcore_certify(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* core,
+                           int32_t* out_code, int64_t* out_vertex, void* stream) {
+  return certify_impl<int64_t>(n, row_ptr, col_idx, core, out_code, out_vertex, (hipStream_t)stream);
 }
 
 kcore_status kcore_decompose_rounds(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,

@@ -31,6 +31,14 @@ def run_gpu(row_ptr, col_idx, int32_rows=False, tuning=None, stats=None):
     return out.cpu().numpy()
 
 
+def certify_gpu(row_ptr, col_idx, core):
+    """The device certificate (kcore_certify) of a coreness vector."""
+    dev = torch.device("cuda:0")
+    return kc().certify(torch.from_numpy(np.ascontiguousarray(row_ptr, dtype=np.int64)).to(dev),
+                        torch.from_numpy(np.ascontiguousarray(col_idx, dtype=np.int32)).to(dev),
+                        torch.from_numpy(np.ascontiguousarray(core, dtype=np.int32)).to(dev))
+
+
 def assert_parity(name, row_ptr, col_idx, **kw):
     print(f"[parity] {name}: n={len(row_ptr) - 1} nnz={len(col_idx)} {kw}", flush=True)
     got = run_gpu(row_ptr, col_idx, **kw)
@@ -39,7 +47,40 @@ def assert_parity(name, row_ptr, col_idx, **kw):
         bad = np.nonzero(got != ref)[0]
         raise AssertionError(f"{name}: {bad.size} mismatches, first v={bad[0]} gpu={got[bad[0]]} ref={ref[bad[0]]}")
     assert oracle.check(row_ptr, col_idx, got)[0] == 0
+    assert certify_gpu(row_ptr, col_idx, got) == (0, -1)
     return got
+
+
+def test_device_certificate_agrees_with_the_cpu_one():
+    # the device certificate and the oracle's certificate give the same verdict on planted mistakes
+    g = gg.workload("rmat16")
+    core = oracle.coreness(g.row_ptr, g.col_idx)
+    assert certify_gpu(g.row_ptr, g.col_idx, core) == (0, -1)
+    deg = np.diff(g.row_ptr)
+    rng = np.random.default_rng(4)
+    cases = []
+    bad = core.copy()
+    v = int(np.argmax(deg > 3))
+    bad[v] = deg[v] + 1
+    cases.append(bad)                      # above the degree
+    bad = core.copy()
+    bad[int(np.argmax(deg == 0))] = 1
+    cases.append(bad)                      # isolated vertex with a core
+    bad = core.copy()
+    v = int(np.argmax(core == core.max()))
+    bad[v] = core.max() + 1
+    cases.append(bad)                      # support too small at the raised level
+    bad = np.where(core == core.max(), core - 1, core).astype(np.int32)
+    cases.append(bad)                      # passes locally although it is not the coreness (not maximal)
+    bad = core.copy()
+    bad[rng.integers(0, g.n, 50)] += 3
+    cases.append(bad)
+    for c in cases:
+        code_cpu, v_cpu = oracle.check(g.row_ptr, g.col_idx, c)
+        code_gpu, v_gpu = certify_gpu(g.row_ptr, g.col_idx, c)
+        assert code_gpu == code_cpu, (code_gpu, code_cpu)
+        if code_cpu in (1, 2, 3):
+            assert v_gpu == v_cpu, (v_gpu, v_cpu)
 
 
 # ---------------------------------------------------------------- small fixtures
@@ -223,6 +264,7 @@ def test_full_size_workloads(name):
     print(f"[parity] {name}: rounds={st.rounds} tail={st.tail_rounds} visits={st.edge_visits}", flush=True)
     assert np.array_equal(got, ref)
     assert oracle.check(g.row_ptr, g.col_idx, got)[0] == 0
+    assert certify_gpu(g.row_ptr, g.col_idx, got) == (0, -1)
 
 
 # ---------------------------------------------------------------- schedule independence
@@ -340,9 +382,13 @@ def test_convergence_profile_reaches_the_coreness():
     from paper_2512_00233_amd import convergence
     g = gg.workload("road_512")
     dev = torch.device("cuda:0")
-    rows, total = convergence.profile(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev))
+    ref = oracle.coreness(g.row_ptr, g.col_idx)
+    rows, total = convergence.profile(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev),
+                                      reference=ref)
     assert len(rows) == total and total >= 2
     assert rows[0]["active"] > 0 and rows[-1]["exact_share"] == 1.0
+    errs = [r["mean_abs_err"] for r in rows]
+    assert errs[-1] == 0.0 and errs[0] > 0
 
 
 @pytest.mark.parametrize("name,tuning", [("rmat16", {}), ("rmat20", {}), ("rmat20", dict(tail_threshold=-1)),

@@ -1,0 +1,167 @@
+"""Core maintenance (kcore_update): coreness after edge removals and insertions, started from the
+coreness before them, equals the oracle's coreness of the changed graph, bit for bit."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from tests import small_graphs as sg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def kc():
+    import paper_2512_00233_amd as kc
+    return kc
+
+
+def edges_of(g):
+    """Undirected edges (u < v) of a CSR graph."""
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    m = src < g.col_idx
+    return np.stack([src[m], g.col_idx[m].astype(np.int64)], axis=1)
+
+
+def change(g, n_remove, n_insert, seed):
+    """Graph g with n_remove of its edges removed and n_insert new edges added (seeded)."""
+    rng = np.random.default_rng(seed)
+    e = edges_of(g)
+    rem_idx = rng.choice(e.shape[0], size=min(n_remove, e.shape[0]), replace=False)
+    removed = e[rem_idx]
+    keep = np.ones(e.shape[0], bool)
+    keep[rem_idx] = False
+    existing = set(map(tuple, e.tolist()))
+    ins = set()
+    while len(ins) < n_insert:
+        u, v = (int(x) for x in rng.integers(0, g.n, 2))
+        a, b = min(u, v), max(u, v)
+        if a != b and (a, b) not in existing and (a, b) not in ins:
+            ins.add((a, b))
+    inserted = np.array(sorted(ins), np.int64).reshape(-1, 2)
+    new_e = np.concatenate([e[keep], inserted])
+    g2 = gg.from_edges(g.n, new_e[:, 0], new_e[:, 1])
+    return g2, removed, inserted
+
+
+def run_update(g_new, prev, removed, inserted, in_place=False, tuning=None, stats=None):
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g_new.row_ptr).to(dev)
+    ci = torch.from_numpy(g_new.col_idx).to(dev)
+    pv = torch.from_numpy(np.ascontiguousarray(prev, np.int32)).to(dev)
+    rm = torch.from_numpy(np.ascontiguousarray(removed, np.int32).reshape(-1, 2)).to(dev)
+    ins = torch.from_numpy(np.ascontiguousarray(inserted, np.int32).reshape(-1, 2)).to(dev)
+    out = kc().update(rp, ci, pv, rm, ins, out=pv if in_place else None, tuning=tuning, stats=stats)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def check(name, g, n_remove, n_insert, seed, **kw):
+    g2, removed, inserted = change(g, n_remove, n_insert, seed)
+    prev = oracle.coreness(g.row_ptr, g.col_idx)
+    ref = oracle.coreness(g2.row_ptr, g2.col_idx)
+    print(f"[update] {name}: n={g.n} -{len(removed)} +{len(inserted)} changed={(prev != ref).sum()} {kw}",
+          flush=True)
+    got = run_update(g2, prev, removed, inserted, **kw)
+    if not np.array_equal(got, ref):
+        bad = np.nonzero(got != ref)[0]
+        raise AssertionError(f"{name}: {bad.size} mismatches, first v={bad[0]} gpu={got[bad[0]]} ref={ref[bad[0]]} "
+                             f"prev={prev[bad[0]]}")
+
+
+@pytest.mark.parametrize("name", ["rmat20", "road_512", "rmat16", "er_small"])
+@pytest.mark.parametrize("n_remove,n_insert", [(1, 0), (1000, 0), (0, 1), (0, 1000), (500, 500), (20000, 0)])
+def test_update_matches_oracle(name, n_remove, n_insert):
+    g = gg.workload(name)
+    check(name, g, n_remove, n_insert, seed=n_remove * 7 + n_insert)
+
+
+@pytest.mark.parametrize("tuning", [dict(activation=1), dict(activation=2, deferred=1), dict(tail_threshold=-1),
+                                    dict(no_prune=1, list_cap=1), dict(thread_max_deg=1, group_max_deg=1,
+                                                                       wave_max_deg=1),
+                                    dict(tail_order=1, tail_big=1, tail_threshold=1 << 30)])
+def test_update_tunings_and_in_place(tuning):
+    g = gg.workload("rmat16")
+    t = kc().Tuning(**tuning)
+    check("rmat16", g, 300, 300, seed=5, tuning=t)
+    check("rmat16/in place", g, 300, 300, seed=6, tuning=t, in_place=True)
+
+
+def test_update_degenerate_changes():
+    # no change at all: the old coreness comes back
+    g = gg.workload("road_512")
+    prev = oracle.coreness(g.row_ptr, g.col_idx)
+    none = np.zeros((0, 2), np.int32)
+    assert np.array_equal(run_update(g, prev, none, none), prev)
+    # a clique losing edges down to a path-like remainder, vertices left isolated or with one neighbour
+    n, edges = sg.complete(30)
+    rp, ci = sg.to_csr(n, edges)
+    full = gg.Graph(rp, ci)
+    e = edges_of(full)
+    rng = np.random.default_rng(3)
+    for k in (1, 50, 300, 420, 435):
+        keep = np.ones(e.shape[0], bool)
+        keep[rng.choice(e.shape[0], k, replace=False)] = False
+        g2 = gg.from_edges(n, e[keep, 0], e[keep, 1])
+        ref = oracle.coreness(g2.row_ptr, g2.col_idx)
+        got = run_update(g2, oracle.coreness(rp, ci), e[~keep], none)
+        assert np.array_equal(got, ref), k
+        # and back: insert the same edges into the reduced graph
+        back = run_update(full, ref, none, e[~keep])
+        assert np.array_equal(back, oracle.coreness(rp, ci)), k
+    # a path grown edge by edge from isolated vertices, then the middle edge removed
+    n = 1000
+    cur = gg.from_edges(n, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    core = np.zeros(n, np.int32)
+    for i in range(0, n - 1, 97):
+        src = np.arange(0, i + 1)
+        nxt = gg.from_edges(n, src, src + 1)
+        new_edges = edges_of(nxt)
+        old_edges = set(map(tuple, edges_of(cur).tolist()))
+        added = np.array([x for x in new_edges.tolist() if tuple(x) not in old_edges], np.int64).reshape(-1, 2)
+        core = run_update(nxt, core, none, added)
+        assert np.array_equal(core, oracle.coreness(nxt.row_ptr, nxt.col_idx)), i
+        cur = nxt
+
+
+def test_update_insertions_into_dense_cores():
+    # insertions that raise cores: edges added inside and between dense parts of a power-law graph
+    g = gg.chung_lu(100_000, 2.1, 16, seed=91)
+    for k, seed in ((1, 1), (10, 2), (5000, 3)):
+        check("chung_lu", g, 0, k, seed=seed)
+        check("chung_lu mixed", g, k, k, seed=seed + 10)
+
+
+def test_update_time_against_full_recompute():
+    # the point of an update: a small change costs far less than a full decomposition
+    import time
+    g = gg.workload("rmat20")
+    dev = torch.device("cuda:0")
+    for n_remove, n_insert in ((100, 0), (0, 100)):
+        g2, removed, inserted = change(g, n_remove, n_insert, seed=42)
+        prev = oracle.coreness(g.row_ptr, g.col_idx)
+        rp = torch.from_numpy(g2.row_ptr).to(dev)
+        ci = torch.from_numpy(g2.col_idx).to(dev)
+        pv = torch.from_numpy(prev).to(dev)
+        rm = torch.from_numpy(removed.astype(np.int32).reshape(-1, 2)).to(dev)
+        ins = torch.from_numpy(inserted.astype(np.int32).reshape(-1, 2)).to(dev)
+        out = torch.empty_like(pv)
+        for _ in range(2):
+            kc().update(rp, ci, pv, rm, ins, out=out)
+            kc().decompose(rp, ci, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            kc().update(rp, ci, pv, rm, ins, out=out)
+        torch.cuda.synchronize()
+        t_upd = (time.perf_counter() - t0) / 5
+        got = out.cpu().numpy()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            kc().decompose(rp, ci, out=out)
+        torch.cuda.synchronize()
+        t_full = (time.perf_counter() - t0) / 5
+        print(f"[update] rmat20 -{n_remove} +{n_insert}: update {t_upd * 1e3:.3f} ms, full {t_full * 1e3:.3f} ms",
+              flush=True)
+        assert np.array_equal(got, out.cpu().numpy())
+        assert np.array_equal(got, oracle.coreness(g2.row_ptr, g2.col_idx))
