@@ -95,9 +95,105 @@ def pmc(fetch_csv: str, write_csv: str, copy_bytes: int, command_fetch: str, com
     return out
 
 
+def _all_counter_means(counter_csv: str) -> dict:
+    """kernel -> counter -> (mean value per dispatch, dispatches), and kernel -> list of per-dispatch rows
+    in dispatch order (for picking out the calibration dispatches)."""
+    acc = defaultdict(lambda: defaultdict(list))
+    order = defaultdict(list)
+    for r in csv.DictReader(open(counter_csv)):
+        acc[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        order[r["Kernel_Name"]].append((int(r.get("Dispatch_Id", 0) or 0), r["Counter_Name"], float(r["Counter_Value"])))
+    return acc, order
+
+
+def counters(csvs, workload: str, commands, kernels, source_hash: str, out_json: str, out_md: str,
+             read_calib_entries: int = 0) -> dict:
+    """Per-kernel means per dispatch of every counter of several rocprofv3 --pmc runs (one counter group per
+    run), with the derived figures: read bytes from the request-size counters, L2 hit rate, mean waves per
+    compute unit, share of wave time waiting."""
+    per = defaultdict(dict)
+    calib = {}
+    for path in csvs:
+        acc, order = _all_counter_means(path)
+        for k, cs in acc.items():
+            short = _short(k)
+            for c, vals in cs.items():
+                if short.startswith("(anonymous namespace)::k_probe_gather") and read_calib_entries:
+                    # the first dispatch is the sequential read calibration, the others the gather probe
+                    first_id = min(d for d, cn, _ in order[k] if cn == c)
+                    cal = [v for d, cn, v in order[k] if cn == c and d == first_id]
+                    rest = [v for d, cn, v in order[k] if cn == c and d != first_id]
+                    calib[c] = cal[0]
+                    if rest:
+                        per["k_probe_gather (rmat24 adjacency)"][c] = (sum(rest) / len(rest), len(rest))
+                    continue
+                per[short][c] = (sum(vals) / len(vals), len(vals))
+    rows = {}
+    for k in kernels:
+        if k not in per:
+            continue
+        c = {name: v for name, (v, _) in per[k].items()}
+        d = {"dispatches": max(n for _, n in per[k].values()), "counters": {n: round(v, 1) for n, v in c.items()}}
+        if all(x in c for x in ("TCC_EA0_RDREQ_32B", "TCC_EA0_RDREQ_64B", "TCC_EA0_RDREQ_128B")):
+            d["read_bytes"] = int(32 * c["TCC_EA0_RDREQ_32B"] + 64 * c["TCC_EA0_RDREQ_64B"] +
+                                  128 * c["TCC_EA0_RDREQ_128B"])
+        if "TCC_EA0_WRREQ" in c and "TCC_EA0_WRREQ_64B" in c:
+            d["write_bytes"] = int(32 * (c["TCC_EA0_WRREQ"] - c["TCC_EA0_WRREQ_64B"]) + 64 * c["TCC_EA0_WRREQ_64B"])
+        if "TCC_HIT" in c and "TCC_MISS" in c and c["TCC_HIT"] + c["TCC_MISS"] > 0:
+            d["l2_hit_rate"] = round(c["TCC_HIT"] / (c["TCC_HIT"] + c["TCC_MISS"]), 4)
+        if "SQ_WAVE_CYCLES" in c and "GRBM_GUI_ACTIVE" in c and c["GRBM_GUI_ACTIVE"] > 0:
+            d["mean_waves_per_cu"] = round(4 * c["SQ_WAVE_CYCLES"] / c["GRBM_GUI_ACTIVE"] / 256, 2)
+        if "SQ_WAIT_INST_ANY" in c and "SQ_WAVE_CYCLES" in c and c["SQ_WAVE_CYCLES"] > 0:
+            d["wait_inst_share"] = round(c["SQ_WAIT_INST_ANY"] / c["SQ_WAVE_CYCLES"], 4)
+        if "SQ_WAIT_ANY" in c and "SQ_WAVE_CYCLES" in c and c["SQ_WAVE_CYCLES"] > 0:
+            d["wait_any_share"] = round(c["SQ_WAIT_ANY"] / c["SQ_WAVE_CYCLES"], 4)
+        if "SQ_ACTIVE_INST_VALU" in c and "SQ_WAVE_CYCLES" in c and c["SQ_WAVE_CYCLES"] > 0:
+            d["valu_share"] = round(c["SQ_ACTIVE_INST_VALU"] / c["SQ_WAVE_CYCLES"], 4)
+        rows[k] = d
+    out = {"workload": workload, "source_hash": source_hash, "commands": commands, "kernels": rows}
+    if calib and read_calib_entries:
+        known = 8 * read_calib_entries
+        rb = 32 * calib.get("TCC_EA0_RDREQ_32B", 0) + 64 * calib.get("TCC_EA0_RDREQ_64B", 0) + \
+            128 * calib.get("TCC_EA0_RDREQ_128B", 0)
+        out["read_calibration"] = {"entries": read_calib_entries, "known_read_bytes": known,
+                                   "request_size_bytes": int(rb) if rb else None,
+                                   "FETCH_SIZE_bytes": int(calib["FETCH_SIZE"] * 1024) if "FETCH_SIZE" in calib else None}
+    json.dump(out, open(out_json, "w"), indent=1)
+    lines = [f"# Hardware counters per dispatch, {workload}", "",
+             "Means per dispatch of rocprofv3 counters, one counter group per run (commands below; each pass is",
+             "a separate process running the same bench command).  Derived: read bytes = 32, 64 and 128 times",
+             "the L2-to-fabric read requests of each size; write bytes likewise; mean waves per compute unit =",
+             "4 * SQ_WAVE_CYCLES / GRBM_GUI_ACTIVE / 256; wait share = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES.", "",
+             "Commands:", "", "```", *commands, "```", ""]
+    if "read_calibration" in out:
+        rc = out["read_calibration"]
+        lines += [f"Read calibration: one sequential pass over {rc['entries']} indices and values "
+                  f"({rc['known_read_bytes']} bytes read): request-size counters {rc['request_size_bytes']} bytes, "
+                  f"FETCH_SIZE {rc['FETCH_SIZE_bytes']} bytes.", ""]
+    keys = ["read_bytes", "write_bytes", "l2_hit_rate", "mean_waves_per_cu", "wait_inst_share", "wait_any_share",
+            "valu_share"]
+    lines += ["| kernel | dispatches | " + " | ".join(keys) + " |", "|---|---:|" + "---:|" * len(keys)]
+    for k, d in rows.items():
+        lines.append(f"| `{k}` | {d['dispatches']} | " + " | ".join(str(d.get(x, "")) for x in keys) + " |")
+    lines += ["", "Raw counter means:", ""]
+    for k, d in rows.items():
+        lines.append(f"- `{k}`: " + ", ".join(f"{n} {v}" for n, v in sorted(d["counters"].items())))
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csvs", nargs="+")
+    c.add_argument("--workload", required=True)
+    c.add_argument("--commands-file", required=True, help="text file, one command per line")
+    c.add_argument("--kernels", required=True, help="comma list of short kernel names")
+    c.add_argument("--source-hash", default="")
+    c.add_argument("--read-calib-entries", type=int, default=0)
+    c.add_argument("--out-json", required=True)
+    c.add_argument("--out-md", required=True)
     a = sub.add_parser("kernel-stats")
     a.add_argument("stats_csv")
     a.add_argument("--command", required=True)
@@ -114,6 +210,11 @@ def main():
     b.add_argument("--out-json", required=True)
     b.add_argument("--out-md", required=True)
     args = ap.parse_args()
+    if args.cmd == "counters":
+        cmds = [line.rstrip("\n") for line in open(args.commands_file) if line.strip()]
+        counters(args.csvs, args.workload, cmds, args.kernels.split(";"), args.source_hash, args.out_json,
+                 args.out_md, args.read_calib_entries)
+        return
     if args.cmd == "kernel-stats":
         kernel_stats(args.stats_csv, args.command, args.title, args.out)
     else:
