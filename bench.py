@@ -59,9 +59,10 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload, kernel):
-    """HBM-side bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"pmc_{workload}.json")
+    """L2-to-memory bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source; else None.  Read bytes come from the read-request counters by size (32, 64 and
+    128 bytes), write bytes likewise: no calibration factor is involved."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -69,9 +70,9 @@ def measured_traffic(workload, kernel):
     if d.get("source_hash") != kernel_source_hash():
         return None
     k = d.get("kernels", {}).get(kernel)
-    if not k:
+    if not k or "read_bytes" not in k or "write_bytes" not in k:
         return None
-    return k.get("bytes_per_launch_scaled")
+    return int(k["read_bytes"] + k["write_bytes"])
 
 
 def host_cpu():

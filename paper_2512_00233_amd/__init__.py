@@ -56,7 +56,8 @@ class Tuning(ctypes.Structure):
         ("tail_order", ctypes.c_int32),
         ("tail_big", ctypes.c_int32),
         ("round_renorm", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("big_wave", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -70,6 +71,8 @@ KERNEL_SYMBOLS = {
     "compact": "k_compact<false, long>",
     "defer": "k_defer<long>",
 }
+# the class-3 wavefront pass of later rounds runs before k_big and counts its work with it
+BIG_WAVE_SYMBOL = "k_big_wave<false, long>"
 
 
 class KernelStats(ctypes.Structure):

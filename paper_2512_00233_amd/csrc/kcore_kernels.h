@@ -68,6 +68,10 @@ constexpr int kWaveRegs = 8;        // class 2: 64 lanes x 8 values
 constexpr int kWaveMaxDeg = kWave * kWaveRegs;           // 512
 constexpr int kBigBlock = 256;      // class 3: one workgroup per vertex
 constexpr int kBigRegs = 8;         // values per thread held in registers (2048 per workgroup)
+// Later rounds: a first class-3 pass takes each vertex on one wavefront when its pruned list has at most
+// kWave * kBigWaveRegs entries (most pruned lists hold a few hundred) and hands the others to the
+// workgroup-per-vertex kernel
+constexpr int kBigWaveRegs = 16;
 // Thresholds per pass of the k-ary search.  Each costs R ballots per pass and
 // the number of passes falls like log_k of the interval, so few thresholds are
 // cheapest (measured on rmat24: 3 best, 2 and 4 within 0.3%, 8 3% slower, 16 15%).
@@ -124,6 +128,7 @@ struct Ctl {
   // longest full adjacency scan of the class-3 kernel: over the run by kernel, and in the current round
   uint32_t maxscan_run[5];
   uint32_t maxscan_round;
+  int32_t resid_cnt;              // class-3 vertices the wavefront pass handed to the workgroup kernel this round
   // deferred same-kernel checks appended in the current round, one counter per
   // buffer region (a workgroup appends to region blockIdx.x % kDeferRegions)
   int32_t dcnt[128];
@@ -179,6 +184,7 @@ struct Args {
   int32_t tail_cap;    // rounds per tail launch before the frontier is handed back (kTailRoundCap)
   int32_t tail_order;  // 1: the tail takes its frontier lowest estimate first, a bounded amount of work per step
   int32_t tail_big;    // 1: class-3 vertices may enter the tail (64 work units each)
+  int32_t big_wave;    // 1: later rounds run the wavefront pass over class 3 first (needs slist for the hand-over)
 };
 
 // A served graph's place in the arenas.

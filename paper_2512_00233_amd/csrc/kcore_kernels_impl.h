@@ -793,6 +793,81 @@ __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t
   return lo + (int32_t)(best >> 32);
 }
 
+// A class-3 vertex whose pruned list holds at most kWave * kBigWaveRegs
+// entries, on one wavefront: the search over that list with the values in
+// registers (ballots only, no barrier).  Returns true when the vertex is done:
+// its value was found there (h >= L) and the update, the compaction of the list
+// and the activation are written, or its estimate is already final.  Returns
+// false, having written nothing but statistics, when the vertex needs the
+// workgroup: no pruned list, a longer one, or a result below L.
+template <bool BATCH, typename Off>
+__device__ __forceinline__ bool upd_big_wave(const Args<Off>& a, const Sink& s, int32_t u, int32_t round,
+                                             LaneStats& st) {
+  constexpr int R = kBigWaveRegs;
+  const int lane = lane_id();
+  const int32_t e = uni(est_val(a.est[u]));
+  if (e < 2) return true;
+  const int32_t pl = a.prune ? uni(a.plen[u]) : 0;
+  if (pl <= 0 || pl > kWave * R) return false;
+  const Off beg = a.row_ptr[u];
+  const int32_t L = uni(a.plow[u]);
+  const int32_t gb = BATCH ? uni(a.vbase[u]) : 0;
+  int32_t c[R], x[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int j = lane + kWave * i;
+    c[i] = (kWave * i < pl && j < pl) ? a.pruned[beg + j] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int j = lane + kWave * i;
+    x[i] = (kWave * i < pl && j < pl) ? a.est[c[i]] : 0;
+  }
+  uint32_t cb = 0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    cb |= (uint32_t)est_cls(x[i]) << (2 * i);
+    x[i] = est_val(x[i]);
+  }
+  if (lane == 0) st.v[ST_VISITS] += pl;
+  int32_t cnt = 0;
+  const int32_t h = kary_regs<kWave, R>(x, e, L, true, cnt);
+  if (h < L) return false;
+  if (lane == 0) st.v[ST_UPDATES] += 1;
+  // entries fallen below L never rise again: compact the list once 1/kPruneCompactDen of it has
+  int32_t kept = 0;
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+    if (kWave * i < pl) kept += popc(ballot(lane + kWave * i < pl && x[i] >= L));
+  if ((pl - kept) * kPruneCompactDen >= pl) {
+    int32_t off = 0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (kWave * i < pl) {
+        const bool keep = lane + kWave * i < pl && x[i] >= L;
+        const uint64_t m = ballot(keep);
+        if (keep) a.pruned[beg + off + lanes_below(m)] = c[i];
+        off += popc(m);
+      }
+    }
+    if (lane == 0) {
+      a.plen[u] = kept;
+      st.v[ST_PRUNE_WRITES] += kept;
+    }
+  }
+  if (lane == 0) a.slack[u] = cnt - h;
+  if (h == e) return true;
+  if (lane == 0) {
+    a.est[u] = est_enc(h, 3);
+    st.v[ST_CHANGES] += 1;
+  }
+  bool in[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) in[i] = lane + kWave * i < pl;
+  activate_changed<R, true>(a, s, c, x, in, e, h, false, round, st, gb, cb);
+  return true;
+}
+
 // One workgroup per vertex of class 3.  Lists of up to BLOCK * kBigRegs entries
 // are held in registers (k-ary search); longer ones use the one-pass LDS
 // histogram.  The pruned list is tried first.  When a search over it succeeds
@@ -800,7 +875,8 @@ __device__ __forceinline__ int32_t hist_search(const Args<Off>& a, const int32_t
 // threshold L (they can never rise again), the list is compacted in place.
 template <int BLOCK, bool BATCH, typename Off>
 __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32_t u, bool dense, int32_t round,
-                                        LaneStats& st, int32_t* red, int32_t* hist, uint16_t* stash, bool track) {
+                                        LaneStats& st, int32_t* red, int32_t* hist, uint16_t* stash, bool track,
+                                        bool wave_tried) {
   constexpr int R = kBigRegs;
   constexpr int CAPR = BLOCK * R;
   const int tid = threadIdx.x;
@@ -843,7 +919,8 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
   if (tid == 0) st.v[ST_UPDATES] += 1;
   int32_t h = -1, cnt = 0;
   bool compact_pass = false;  // the streaming pass compacts the pruned list
-  if (pl > 0) {
+  // a pruned list short enough for the wavefront pass was searched there already, without success
+  if (pl > 0 && !(wave_tried && pl <= kWave * kBigWaveRegs)) {
     if (tid == 0) st.v[ST_VISITS] += pl;
     if (pl <= CAPR) {
       load(a.pruned, pl, 0);
@@ -1434,7 +1511,10 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
   const int32_t round = ctl->rbase + slot;
   // this round's deferred checks start empty (the previous round's were consumed by its k_defer)
   if (!SEED && blockIdx.x == 0 && threadIdx.x < kDeferRegions) ctl->dcnt[threadIdx.x] = 0;
-  if (!SEED && blockIdx.x == 0 && threadIdx.x == 0) ctl->maxscan_round = 0;
+  if (!SEED && blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->maxscan_round = 0;
+    ctl->resid_cnt = 0;
+  }
   if (!SEED && ctl->overflow[round % 3][0] == 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int64_t n = a.served ? (int64_t)ctl->nhi : a.n;  // served graphs: the range of the live slots
@@ -1552,6 +1632,39 @@ __global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t slot, int3
   }
 }
 
+// Later rounds, class 3, first pass (before k_big): one wavefront per vertex.
+// A vertex whose pruned list is short and holds the answer is finished here;
+// the others go to the hand-over list (the class-3 region of the first-round
+// list, unused after the first round), which k_big then takes one workgroup per
+// vertex.  Both kernels run before the classes-0..2 kernel, so the activation
+// rules see them as one class-3 kernel (a class-3 neighbour is always a
+// same-kernel neighbour).
+template <bool BATCH, typename Off>
+__global__ __launch_bounds__(256) void k_big_wave(Args<Off> a, int32_t slot, int32_t collect_stats) {
+  __shared__ unsigned long long red64[kLaneStats * (256 / kWave)];
+  Ctl* ctl = a.ctl;
+  const int32_t round = ctl->rbase + slot;
+  bool dense = false;
+  const Frontier f = frontier_of<false>(a, round, dense);
+  if (f.n[3] == 0 || tail_eligible(a, f, dense)) return;
+  LaneStats st;
+  const int nslot = (round + 1) % 3;
+  Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
+  if (a.defer) {
+    const int reg = blockIdx.x % kDeferRegions;
+    s.dcnt = &ctl->dcnt[reg];
+    s.dcap = a.defer_cap / kDeferRegions;
+    s.dbase = reg * s.dcap;
+  }
+  int32_t* hand = a.slist + f.b[3];
+  const int32_t nw = (int32_t)(gridDim.x * (256 / kWave));
+  for (int32_t i = (int32_t)(blockIdx.x * (256 / kWave) + threadIdx.x / kWave); i < f.n[3]; i += nw) {
+    const int32_t u = uni(f.list[f.b[3] + i]);
+    if (!upd_big_wave<BATCH>(a, s, u, round, st) && lane_id() == 0) hand[atomicAdd(&ctl->resid_cnt, 1)] = u;
+  }
+  if (collect_stats) flush_stats<256>(ctl, KI_BIG, st, red64);
+}
+
 // One round, class 3 (degree above the wavefront class): one workgroup per
 // vertex.  Runs before k_round of the same round; a round handed to the tail
 // has no class-3 vertex, so this kernel then finds nothing to do.
@@ -1577,9 +1690,13 @@ __global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot,
     s.dcap = a.defer_cap / kDeferRegions;
     s.dbase = reg * s.dcap;
   }
-  for (int32_t i = blockIdx.x; i < f.n[3]; i += gridDim.x) {
-    const int32_t u = f.list[f.b[3] + i];
-    upd_big<BLOCK, BATCH>(a, s, u, FIRST, round, st, red, hist, stash, collect_stats != 0);
+  // later rounds with the wavefront pass: only the vertices it handed over, from the hand-over list
+  const bool resid = !FIRST && a.big_wave;
+  const int32_t n3 = resid ? ld_counter(&ctl->resid_cnt) : f.n[3];
+  const int32_t* l3 = resid ? a.slist + f.b[3] : f.list + f.b[3];
+  for (int32_t i = blockIdx.x; i < n3; i += gridDim.x) {
+    const int32_t u = l3[i];
+    upd_big<BLOCK, BATCH>(a, s, u, FIRST, round, st, red, hist, stash, collect_stats != 0, resid);
     if (FIRST && kBigFirst) {
       // every class-3 vertex is in the second round's frontier
       int32_t self[1] = {u};

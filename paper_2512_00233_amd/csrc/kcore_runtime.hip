@@ -227,6 +227,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.tail_order = 0;
   r.tail_big = 0;
   r.renorm = kRoundRenorm;
+  r.big_wave = 1;
   if (const char* e = std::getenv("KCORE_TAIL")) {
     r.tail = std::atoi(e);
     r.tail_auto = 0;
@@ -260,6 +261,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
     if (t->tail_round_cap > 0) r.tail_cap = t->tail_round_cap;
     r.tail_order = t->tail_order == 1;
     r.tail_big = t->tail_big == 1;
+    if (t->big_wave == 1 || t->big_wave == 2) r.big_wave = t->big_wave == 1;
     if (t->round_renorm > 0) r.renorm = std::max(t->round_renorm, 1024);
     if (t->max_rounds > 0) {
       r.max_rounds = t->max_rounds;
@@ -345,6 +347,8 @@ template <bool FIRST, bool BATCH, typename Off>
 static void launch_updates(const Args<Off>& a, const Tuning& tu, int32_t slot, int32_t collect, hipStream_t st,
                            hipEvent_t* ev) {
   if (ev) (void)hipEventRecord(ev[0], st);
+  if (!FIRST && a.big_wave)
+    hipLaunchKernelGGL((k_big_wave<BATCH, Off>), dim3(tu.big_grid), dim3(256), 0, st, a, slot, collect);
   if (kBigFirst)
     hipLaunchKernelGGL((k_big<FIRST, BATCH, Off>), dim3(tu.big_grid), dim3(kBigBlock), 0, st, a, slot, collect);
   else
@@ -488,6 +492,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   a.tail_cap = tu.tail_cap;
   a.tail_order = tu.tail_order;
   a.tail_big = tu.tail_big;
+  a.big_wave = tu.big_wave && a.slist && a.prune;
   const int32_t collect = (stats || rec) ? 1 : 0;
   const bool trace_env = env_flag("KCORE_TRACE");
   const bool trace = trace_env || rec != nullptr;  // one round per launch, counters read after each
