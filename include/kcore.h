@@ -96,9 +96,10 @@ typedef struct kcore_tuning {
                               between two chunks of rounds (0: 2^30; values below 1024 are raised to 1024).
                               Round numbers therefore never overflow, however many rounds or served steps
                               a call or a server runs; a test hook, results never depend on it */
-  int32_t big_wave;        /* later rounds of single graphs and batches: 1 (default) a first class-3 pass takes each
-                              vertex on one wavefront when its pruned list has at most 1024 entries, and hands
-                              the rest to the workgroup-per-vertex kernel; 2 every class-3 vertex on a workgroup */
+  int32_t big_wave;        /* later rounds of single graphs and batches: 1 a first class-3 pass takes each vertex
+                              on one wavefront when its pruned list has at most 1024 entries, and hands the rest
+                              to the workgroup-per-vertex kernel; 0 or 2 (default) every class-3 vertex on a
+                              workgroup (measured faster on rmat24, road and ER small) */
   int32_t reserved[3];
 } kcore_tuning;
 

@@ -68,9 +68,10 @@ constexpr int kWaveRegs = 8;        // class 2: 64 lanes x 8 values
 constexpr int kWaveMaxDeg = kWave * kWaveRegs;           // 512
 constexpr int kBigBlock = 256;      // class 3: one workgroup per vertex
 constexpr int kBigRegs = 8;         // values per thread held in registers (2048 per workgroup)
-// Later rounds: a first class-3 pass takes each vertex on one wavefront when its pruned list has at most
-// kWave * kBigWaveRegs entries (most pruned lists hold a few hundred) and hands the others to the
-// workgroup-per-vertex kernel
+// Later rounds, optional (kcore_tuning.big_wave = 1): a first class-3 pass takes each vertex on one
+// wavefront when its pruned list has at most kWave * kBigWaveRegs entries (most pruned lists hold a few
+// hundred) and hands the others to the workgroup-per-vertex kernel.  Measured slower on rmat24 (26.3 ms
+// against 25.3 ms: the pass and the hand-over cost more than the concurrency gains), so it is off by default.
 constexpr int kBigWaveRegs = 16;
 // Thresholds per pass of the k-ary search.  Each costs R ballots per pass and
 // the number of passes falls like log_k of the interval, so few thresholds are
@@ -90,6 +91,10 @@ constexpr int kPruneMarginDen = 4;
 constexpr int kPruneFirstMarginDen = 3;
 constexpr int kDeferRegions = 128;  // regions of the deferred-check buffer (spreads the append counters)
 constexpr int kPruneCompactDen = 16;  // a class-3 pruned list is compacted once >= 1/16 of it is below L
+// Lists longer than this (hubs) are rebuilt with the wider threshold L = h / 2: a full rescan of a hub by one
+// workgroup takes longer than a whole round elsewhere, so hubs trade a longer pruned list for fewer
+// rescans (rmat24: 24.9 ms against 25.3 ms with the h - h/4 of other lists)
+constexpr int kHubPruneDeg = 16384;
 
 // During a run the estimate array holds value << 2 | degree class (classes
 // 0..3; a vertex of degree <= 1 is stored as class 0, it is never activated),

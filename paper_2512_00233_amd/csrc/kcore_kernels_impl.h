@@ -1024,7 +1024,7 @@ __device__ __forceinline__ void upd_big(const Args<Off>& a, const Sink& s, int32
   // the barrier that follows its read, and never ahead of the positions read)
   constexpr int U = 8;
   const bool write_pass = rebuild_pass || compact_pass;
-  const int32_t L2 = compact_pass ? L : (dense ? prune_low_first(h) : prune_low(h));
+  const int32_t L2 = compact_pass ? L : (d > kHubPruneDeg ? max(2, h / 2) : (dense ? prune_low_first(h) : prune_low(h)));
   int32_t written = 0;
   for (int32_t j0 = 0; j0 < len; j0 += BLOCK * U) {
     int32_t v[U], xv[U];

@@ -227,7 +227,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.tail_order = 0;
   r.tail_big = 0;
   r.renorm = kRoundRenorm;
-  r.big_wave = 1;
+  r.big_wave = 0;
   if (const char* e = std::getenv("KCORE_TAIL")) {
     r.tail = std::atoi(e);
     r.tail_auto = 0;

@@ -98,7 +98,7 @@ def test_batch_edge_cases():
                                     dict(activation=1, no_prune=1), dict(activation=2), dict(deferred=1),
                                     dict(tail_order=1, tail_big=1, tail_threshold=1 << 30),
                                     dict(tail_round_cap=2, tail_threshold=1 << 30),
-                                    dict(round_renorm=1024, rounds_per_poll=1), dict(big_wave=2),
+                                    dict(round_renorm=1024, rounds_per_poll=1), dict(big_wave=1),
                                     dict(thread_max_deg=1, group_max_deg=1, wave_max_deg=1, big_wave=1)])
 def test_batch_tunings(tuning):
     b = gg.batch(16, seed=5, nmin=1000, nmax=30_000)

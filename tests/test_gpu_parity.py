@@ -295,9 +295,9 @@ TUNINGS = {
     "tail_with_class3_lowest_first": dict(tail_big=1, tail_order=1, tail_threshold=1 << 30),
     "tail_cap_3": dict(tail_round_cap=3, tail_threshold=1 << 30),
     "tail_cap_1_lowest_first": dict(tail_round_cap=1, tail_order=1, tail_big=1, tail_threshold=1 << 30),
-    "no_class3_wave_pass": dict(big_wave=2),
-    "no_class3_wave_pass_deferred": dict(big_wave=2, deferred=1, list_cap=512),
-    "class3_wave_pass_everything": dict(thread_max_deg=1, group_max_deg=1, wave_max_deg=1, deferred=1),
+    "class3_wave_pass": dict(big_wave=1),
+    "class3_wave_pass_deferred": dict(big_wave=1, deferred=1, list_cap=512),
+    "class3_wave_pass_everything": dict(thread_max_deg=1, group_max_deg=1, wave_max_deg=1, deferred=1, big_wave=1),
     "renumber_often": dict(round_renorm=1024, rounds_per_poll=1),
     "renumber_often_deferred": dict(round_renorm=1024, deferred=1, no_graph=1),
 }
