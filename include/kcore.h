@@ -100,7 +100,10 @@ typedef struct kcore_tuning {
                               on one wavefront when its pruned list has at most 1024 entries, and hands the rest
                               to the workgroup-per-vertex kernel; 0 or 2 (default) every class-3 vertex on a
                               workgroup (measured faster on rmat24, road and ER small) */
-  int32_t reserved[3];
+  int32_t dense_sweep;     /* rounds that rebuild their lists from the round stamps: 1 (default) later-round
+                              activations also mark their piece of 1024 vertices and the rebuild reads only
+                              marked pieces; 2 the rebuild reads every stamp */
+  int32_t reserved[2];
 } kcore_tuning;
 
 /* Round kernels, as indices into kcore_stats.kernel.  The first round (every

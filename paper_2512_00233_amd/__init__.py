@@ -57,7 +57,8 @@ class Tuning(ctypes.Structure):
         ("tail_big", ctypes.c_int32),
         ("round_renorm", ctypes.c_int32),
         ("big_wave", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("dense_sweep", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 

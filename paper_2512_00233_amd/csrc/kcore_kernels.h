@@ -80,6 +80,9 @@ constexpr int kKary = 3;
 constexpr int kHistBins = 4096;     // LDS histogram bins of the one-pass search (16 KB)
 constexpr int kStash = 8192;        // LDS copies (16-bit) of the values read by the one-pass search (16 KB)
 constexpr int kCompactPerLane = 16; // vertices per lane read at once by the compaction kernel
+constexpr int kCompactPiece = 64 * kCompactPerLane;  // vertices a wavefront reads at once (a dirty-mark piece)
+constexpr int kCompactPieceShift = 10;
+static_assert(kCompactPiece == 1 << kCompactPieceShift, "piece size");
 constexpr int kRelabelBuckets = 1024;  // degree buckets of the relabelling (larger degrees share the top one)
 constexpr int kRelabelLongDeg = 64;    // rows above this degree are copied by a wavefront when renumbering
 // Order of the two update kernels in a round: class 3 first (true) or classes 0..2 first.
@@ -134,6 +137,7 @@ struct Ctl {
   uint32_t maxscan_run[5];
   uint32_t maxscan_round;
   int32_t resid_cnt;              // class-3 vertices the wavefront pass handed to the workgroup kernel this round
+  int32_t dirty_from;             // first round whose compaction may skip pieces without a dirty mark
   // deferred same-kernel checks appended in the current round, one counter per
   // buffer region (a workgroup appends to region blockIdx.x % kDeferRegions)
   int32_t dcnt[128];
@@ -190,6 +194,11 @@ struct Args {
   int32_t tail_order;  // 1: the tail takes its frontier lowest estimate first, a bounded amount of work per step
   int32_t tail_big;    // 1: class-3 vertices may enter the tail (64 work units each)
   int32_t big_wave;    // 1: later rounds run the wavefront pass over class 3 first (needs slist for the hand-over)
+  // Dirty pieces (kCompactPiece vertices each), two arrays by the parity of the stamped round: every later-round
+  // activation marks its piece, so that a round that rebuilds its lists from the stamps skips unmarked pieces
+  // (nullptr: every piece is read)
+  uint8_t* dirty;
+  int64_t dirty_pieces;  // pieces per parity
 };
 
 // A served graph's place in the arenas.

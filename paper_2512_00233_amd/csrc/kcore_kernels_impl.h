@@ -62,6 +62,7 @@ struct Sink {
   int32_t* dcnt;      // this workgroup's deferred-check counter (nullptr: re-activate instead)
   int32_t dbase;      // first triple of its buffer region
   int32_t dcap;       // triples in the region
+  uint8_t* dirty;     // dirty-piece marks of the next round (nullptr: none kept)
 };
 
 template <typename Off>
@@ -75,6 +76,7 @@ __device__ __forceinline__ Sink make_sink(const Args<Off>& a, int32_t next_round
   s.dcnt = nullptr;
   s.dbase = 0;
   s.dcap = 0;
+  s.dirty = a.dirty ? a.dirty + (next_round & 1) * a.dirty_pieces : nullptr;
   region_bases(a.ctl, s.b);
 #pragma unroll
   for (int k = 0; k < kClasses; ++k) s.cap[k] = capped ? min(a.ctl->pop[k], a.list_cap) : a.ctl->pop[k];
@@ -135,7 +137,10 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
     // stamps: plain stores (all writers of this round store the same value)
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (cand[i]) a.stamp[v[i]] = s.stamp;
+      if (cand[i]) {
+        a.stamp[v[i]] = s.stamp;
+        if (s.dirty) s.dirty[v[i] >> kCompactPieceShift] = 1;
+      }
     uint32_t nc = 0;
 #pragma unroll
     for (int i = 0; i < N; ++i) nc += cand[i];
@@ -199,7 +204,10 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
     // the next round's lists come from the stamps: no dedup needed, plain stores
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (want >> i & 1u) a.stamp[v[i]] = s.stamp;
+      if (want >> i & 1u) {
+        a.stamp[v[i]] = s.stamp;
+        if (s.dirty) s.dirty[v[i] >> kCompactPieceShift] = 1;
+      }
     st.v[ST_ACTIVATIONS] += __popc(want);
     if (a.gact && want) a.gact[gb] = s.stamp;
     return;
@@ -210,6 +218,12 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
 #pragma unroll
   for (int i = 0; i < N; ++i) first |= (p[i] < s.stamp ? 1u : 0u) << i;
   st.v[ST_ACTIVATIONS] += __popc(first);
+  // the next round may still overflow its lists and rebuild them from the stamps
+  if (s.dirty) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (first >> i & 1u) s.dirty[v[i] >> kCompactPieceShift] = 1;
+  }
   // served graphs: the graph has work in the next round (all candidates share the current vertex's graph)
   if (a.gact && first) a.gact[gb] = s.stamp;
   if (!ballot(first != 0)) return;
@@ -1323,7 +1337,8 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
     }
     int32_t* ncnt = ctl->tail_cnt[(t + 1) & 1];
     if (a.tail_order) tail_select<BLOCK>(a, f, r, ncnt, bins, red);
-    const Sink s = make_sink(a, r + 1, ncnt, nullptr, false);
+    Sink s = make_sink(a, r + 1, ncnt, nullptr, false);
+    s.dirty = nullptr;  // tail lists are never rebuilt from the stamps
     // the two groups of classes in the order of the round kernels; the barrier
     // makes the first group's updates visible to the second
     if (kBigFirst)
@@ -1449,7 +1464,10 @@ __global__ __launch_bounds__(256) void k_rebase(int32_t* stamp, int32_t* gact, i
     stamp[v] = max(stamp[v] - d, 0);
     if (gact) gact[v] = max(gact[v] - d, 0);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->rbase -= d;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->rbase -= d;
+    ctl->dirty_from = max(ctl->dirty_from - d, 0);
+  }
 }
 
 // Batched graphs: vbase[v] = first global vertex id of v's graph (one workgroup per graph).
@@ -1469,6 +1487,7 @@ __global__ __launch_bounds__(256) void k_init(Args<Off> a, int32_t r0, int32_t t
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.ctl->overflow[(r0 + 1) % 3][0] = 1;
     a.ctl->rbase = r0;
+    a.ctl->dirty_from = r0 + 2;  // the first round's activations are not marked
   }
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   uint32_t p[kClasses] = {0, 0, 0, 0};
@@ -1515,12 +1534,19 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
     ctl->maxscan_round = 0;
     ctl->resid_cnt = 0;
   }
-  if (!SEED && ctl->overflow[round % 3][0] == 0) return;
   const int wave = threadIdx.x / kWave, lane = lane_id();
   const int64_t n = a.served ? (int64_t)ctl->nhi : a.n;  // served graphs: the range of the live slots
   const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + PIECE * NW - 1) / (PIECE * NW) * (PIECE * NW);
   const int64_t wchunk = chunk / NW;
   const int64_t w0 = (int64_t)blockIdx.x * chunk + wave * wchunk, w1 = min(n, w0 + wchunk);
+  static_assert(PIECE == kCompactPiece, "a wavefront piece is a dirty-mark piece");
+  // this round's activations mark the next round's pieces: clear them first (every piece of [0, n) is in
+  // exactly one wavefront's range)
+  if (!SEED && a.dirty && lane == 0)
+    for (int64_t pb = w0; pb < w1; pb += PIECE) a.dirty[((round + 1) & 1) * a.dirty_pieces + (pb >> kCompactPieceShift)] = 0;
+  if (!SEED && ctl->overflow[round % 3][0] == 0) return;
+  // pieces without a mark hold no vertex of this round (every later-round activation marks its piece)
+  const uint8_t* marks = (!SEED && a.dirty && round >= ctl->dirty_from) ? a.dirty + (round & 1) * a.dirty_pieces : nullptr;
   // class of each vertex of a piece (kClasses: not in the list)
   auto piece = [&](int64_t pb, int32_t (&c)[P]) {
     if (SEED) {  // every vertex with a class (degree >= 2)
@@ -1529,6 +1555,11 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
         const int64_t v = pb + i * kWave + lane;
         c[i] = v < w1 ? (int32_t)a.cls[v] : kClasses;
       }
+      return;
+    }
+    if (marks && marks[pb >> kCompactPieceShift] == 0) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) c[i] = kClasses;
       return;
     }
 #pragma unroll
@@ -1618,6 +1649,7 @@ __global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t slot, int3
   }
   const int nslot = (round + 1) % 3;
   Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
+  if (FIRST) s.dirty = nullptr;  // the round after the first reads every piece
   if (!FIRST && a.defer) {
     const int reg = blockIdx.x % kDeferRegions;
     s.dcnt = &ctl->dcnt[reg];
@@ -1684,6 +1716,7 @@ __global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot,
   LaneStats st;
   const int nslot = (round + 1) % 3;
   Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
+  if (FIRST) s.dirty = nullptr;
   if (!FIRST && a.defer) {
     const int reg = blockIdx.x % kDeferRegions;
     s.dcnt = &ctl->dcnt[reg];
@@ -2006,6 +2039,7 @@ __global__ __launch_bounds__(256) void k_upd_init(Args<Off> a, const int32_t* pr
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.ctl->overflow[r % 3][0] = 1;
     a.ctl->rbase = r;
+    a.ctl->dirty_from = r + 1;  // the seeds are not marked: round r reads every piece
   }
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   uint32_t p[kClasses] = {0, 0, 0, 0};

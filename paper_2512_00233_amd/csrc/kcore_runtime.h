@@ -38,6 +38,7 @@ struct Tuning {
   int tail_big;   // 1: class-3 vertices may enter the tail
   int renorm;     // round number above which stamps are renumbered down
   int big_wave;   // 1: later rounds run the wavefront pass over class 3 before the workgroup kernel
+  int dirty;      // 1: later-round activations mark their piece; compaction rounds skip unmarked pieces
 };
 
 Tuning resolve_tuning(const kcore_tuning* t, int num_cus);

@@ -51,6 +51,8 @@ struct Workspace {
   int32_t* slack = nullptr;
   int32_t* defer = nullptr;  // deferred same-kernel checks, 3 ints each
   int64_t defer_cap = 0;
+  uint8_t* dirty = nullptr;  // dirty-piece marks, two arrays (by round parity) of dirty_pieces bytes
+  int64_t dirty_pieces = 0;
   int32_t* pruned = nullptr;
   Ctl* ctl = nullptr;
   Ctl* host_ctl = nullptr;      // pinned
@@ -115,13 +117,15 @@ struct Workspace {
     drop_graphs();
     release_relabel();
     for (void* p : {(void*)stamp, (void*)cls, (void*)lists[0], (void*)lists[1], (void*)slist, (void*)plen,
-                    (void*)plow, (void*)vbase, (void*)slack, (void*)defer, (void*)pruned})
+                    (void*)plow, (void*)vbase, (void*)slack, (void*)defer, (void*)pruned, (void*)dirty})
       (void)hipFree(p);
     stamp = nullptr;
     cls = nullptr;
     lists[0] = lists[1] = nullptr;
     slist = plen = plow = vbase = slack = defer = pruned = nullptr;
+    dirty = nullptr;
     defer_cap = 0;
+    dirty_pieces = 0;
     cap_n = 0;
     cap_nnz = 0;
   }
@@ -180,6 +184,7 @@ static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, bool 
             hipMalloc(&ws->slack, sizeof(int32_t) * cap) == hipSuccess &&
             hipMalloc(&ws->defer, sizeof(int32_t) * 3 * defer_capacity(cap)) == hipSuccess &&
             (!keep_vbase || hipMalloc(&ws->vbase, sizeof(int32_t) * cap) == hipSuccess) &&
+            hipMalloc(&ws->dirty, 2 * ((cap + kCompactPiece - 1) / kCompactPiece)) == hipSuccess &&
 
             hipMalloc(&ws->pruned, sizeof(int32_t) * cap_e) == hipSuccess;
   if (!ok) {
@@ -189,6 +194,8 @@ static kcore_status ensure_capacity(Workspace* ws, int64_t n, int64_t nnz, bool 
                                    " nnz=" + std::to_string(nnz));
   }
   KC_HIP(hipMemsetAsync(ws->stamp, 0, sizeof(int32_t) * cap, st));
+  ws->dirty_pieces = (cap + kCompactPiece - 1) / kCompactPiece;
+  KC_HIP(hipMemsetAsync(ws->dirty, 0, 2 * ws->dirty_pieces, st));
   ws->cap_n = cap;
   ws->cap_nnz = cap_e;
   ws->defer_cap = defer_capacity(cap);
@@ -228,6 +235,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
   r.tail_big = 0;
   r.renorm = kRoundRenorm;
   r.big_wave = 0;
+  r.dirty = 1;
   if (const char* e = std::getenv("KCORE_TAIL")) {
     r.tail = std::atoi(e);
     r.tail_auto = 0;
@@ -262,6 +270,7 @@ Tuning resolve_tuning(const kcore_tuning* t, int num_cus) {
     r.tail_order = t->tail_order == 1;
     r.tail_big = t->tail_big == 1;
     if (t->big_wave == 1 || t->big_wave == 2) r.big_wave = t->big_wave == 1;
+    if (t->dense_sweep == 1 || t->dense_sweep == 2) r.dirty = t->dense_sweep == 1;
     if (t->round_renorm > 0) r.renorm = std::max(t->round_renorm, 1024);
     if (t->max_rounds > 0) {
       r.max_rounds = t->max_rounds;
@@ -493,6 +502,8 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   a.tail_order = tu.tail_order;
   a.tail_big = tu.tail_big;
   a.big_wave = tu.big_wave && a.slist && a.prune;
+  a.dirty = tu.dirty ? ws->dirty : nullptr;
+  a.dirty_pieces = ws->dirty_pieces;
   const int32_t collect = (stats || rec) ? 1 : 0;
   const bool trace_env = env_flag("KCORE_TRACE");
   const bool trace = trace_env || rec != nullptr;  // one round per launch, counters read after each

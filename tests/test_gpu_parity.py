@@ -295,6 +295,8 @@ TUNINGS = {
     "tail_with_class3_lowest_first": dict(tail_big=1, tail_order=1, tail_threshold=1 << 30),
     "tail_cap_3": dict(tail_round_cap=3, tail_threshold=1 << 30),
     "tail_cap_1_lowest_first": dict(tail_round_cap=1, tail_order=1, tail_big=1, tail_threshold=1 << 30),
+    "full_dense_sweep": dict(dense_sweep=2),
+    "full_dense_sweep_small_cap": dict(dense_sweep=2, list_cap=64, tail_threshold=-1),
     "class3_wave_pass": dict(big_wave=1),
     "class3_wave_pass_deferred": dict(big_wave=1, deferred=1, list_cap=512),
     "class3_wave_pass_everything": dict(thread_max_deg=1, group_max_deg=1, wave_max_deg=1, deferred=1, big_wave=1),
