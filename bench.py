@@ -387,6 +387,68 @@ def run_serve_workload(args, torch, kc, gg, np):
     }
 
 
+def run_update_workload(torch, kc, gg, np, name="rmat20", seed=42):
+    """Core maintenance: kcore_update after batches of edge removals and insertions against a full
+    kcore_decompose of the changed graph (both timed with HIP events, the graph resident); every update result
+    is compared with the full decomposition's and, untimed, with the oracle."""
+    import oracle
+    g = gg.workload(name)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    upper = src < g.col_idx
+    edges = np.stack([src[upper], g.col_idx[upper].astype(np.int64)], axis=1)
+    del src, upper
+    prev = oracle.coreness_bz(g.row_ptr, g.col_idx)
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(seed)
+    rows = []
+    for n_rem, n_ins in ((1, 0), (1000, 0), (100000, 0), (0, 1), (0, 1000), (1000, 1000)):
+        rem_idx = rng.choice(edges.shape[0], size=n_rem, replace=False)
+        keep = np.ones(edges.shape[0], bool)
+        keep[rem_idx] = False
+        ins = set()
+        while len(ins) < n_ins:
+            u, v = (int(x) for x in rng.integers(0, g.n, 2))
+            a, b = min(u, v), max(u, v)
+            if a != b:
+                ins.add((a, b))
+        ins_arr = np.array(sorted(ins), np.int64).reshape(-1, 2)
+        # drop any sampled pair that is already an edge (searchsorted in the sorted rows)
+        if ins_arr.size:
+            lo, hi = g.row_ptr[ins_arr[:, 0]], g.row_ptr[ins_arr[:, 0] + 1]
+            exists = np.array([np.any(g.col_idx[l:h] == b) for l, h, b in zip(lo, hi, ins_arr[:, 1])])
+            ins_arr = ins_arr[~exists]
+        new_e = np.concatenate([edges[keep], ins_arr])
+        g2 = gg.from_edges(g.n, new_e[:, 0], new_e[:, 1])
+        ref = oracle.coreness_bz(g2.row_ptr, g2.col_idx)
+        rp, ci = torch.from_numpy(g2.row_ptr).to(dev), torch.from_numpy(g2.col_idx).to(dev)
+        pv = torch.from_numpy(prev).to(dev)
+        rm = torch.from_numpy(edges[rem_idx].astype(np.int32)).to(dev)
+        it = torch.from_numpy(ins_arr.astype(np.int32)).to(dev)
+        out_u = torch.empty_like(pv)
+        out_f = torch.empty_like(pv)
+        for _ in range(2):
+            kc.update(rp, ci, pv, rm, it, out=out_u)
+            kc.decompose(rp, ci, out=out_f)
+        torch.cuda.synchronize()
+
+        def timed(fn, reps=5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        ms_u = timed(lambda: kc.update(rp, ci, pv, rm, it, out=out_u))
+        ms_f = timed(lambda: kc.decompose(rp, ci, out=out_f))
+        got_u, got_f = out_u.cpu().numpy(), out_f.cpu().numpy()
+        rows.append({"removed": int(n_rem), "inserted": int(ins_arr.shape[0]), "changed": int((ref != prev).sum()),
+                     "update_ms": round(ms_u, 4), "full_ms": round(ms_f, 4), "speedup": round(ms_f / ms_u, 2),
+                     "exact": bool(np.array_equal(got_u, ref) and np.array_equal(got_f, ref))})
+    return {"workload": "update", "graph": name, "n": g.n, "nnz": g.nnz, "batches": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -401,7 +463,7 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=64, help="serve: device arena budget (GiB)")
     ap.add_argument("--rounds-per-step", type=int, default=8, help="serve: rounds between step boundaries")
     ap.add_argument("--autotune", default="", help="batch workload: run the autotuner and save to this JSON")
-    ap.add_argument("--also", default="road,er_small,batch,serve",
+    ap.add_argument("--also", default="road,er_small,batch,serve,update",
                     help="other workloads to report (comma list; batch and serve run reduced versions)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-runs", type=int, default=ROOFLINE_RUNS,
@@ -482,6 +544,10 @@ def main():
 
     also = []
     for name in [w for w in args.also.split(",") if w and w != args.workload]:
+        if name == "update":
+            progress("core maintenance after edge changes (rmat20)")
+            also.append(run_update_workload(torch, kc, gg, np))
+            continue
         if name in ("batch", "serve"):
             # the batched and served forms at their full sizes (2048 graphs; 20,000 requests)
             sub = argparse.Namespace(**vars(args))
