@@ -401,7 +401,7 @@ def run_update_workload(torch, kc, gg, np, name="rmat20", seed=42):
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(seed)
     rows = []
-    for n_rem, n_ins in ((1, 0), (1000, 0), (100000, 0), (0, 1), (0, 1000), (1000, 1000)):
+    for n_rem, n_ins in ((1, 0), (1000, 0), (100000, 0), (0, 1), (0, 100), (0, 1000), (1000, 1000)):
         rem_idx = rng.choice(edges.shape[0], size=n_rem, replace=False)
         keep = np.ones(edges.shape[0], bool)
         keep[rem_idx] = False
@@ -443,9 +443,17 @@ def run_update_workload(torch, kc, gg, np, name="rmat20", seed=42):
         ms_u = timed(lambda: kc.update(rp, ci, pv, rm, it, out=out_u))
         ms_f = timed(lambda: kc.decompose(rp, ci, out=out_f))
         got_u, got_f = out_u.cpu().numpy(), out_f.cpu().numpy()
-        rows.append({"removed": int(n_rem), "inserted": int(ins_arr.shape[0]), "changed": int((ref != prev).sum()),
+        st = kc.Stats()
+        chk = torch.empty_like(pv)
+        kc.update(rp, ci, pv, rm, it, out=chk, stats=st)  # untimed: rounds and recomputations
+        torch.cuda.synchronize()
+        D = int(np.bincount(ins_arr.ravel(), minlength=g.n).max()) if ins_arr.size else 0
+        rows.append({"removed": int(n_rem), "inserted": int(ins_arr.shape[0]), "D": D,
+                     "changed": int((ref != prev).sum()), "update_rounds": int(st.rounds),
+                     "update_recomputations": int(st.vertex_updates),
                      "update_ms": round(ms_u, 4), "full_ms": round(ms_f, 4), "speedup": round(ms_f / ms_u, 2),
-                     "exact": bool(np.array_equal(got_u, ref) and np.array_equal(got_f, ref))})
+                     "exact": bool(np.array_equal(got_u, ref) and np.array_equal(got_f, ref)
+                                   and np.array_equal(chk.cpu().numpy(), ref))})
     return {"workload": "update", "graph": name, "n": g.n, "nnz": g.nnz, "batches": rows}
 
 

@@ -234,8 +234,10 @@ kcore_status kcore_decompose_noalloc(int64_t n, const int64_t* row_ptr, const in
  * through vertices of the smaller endpoint's coreness, so the vertices that
  * reach an inserted endpoint (in the new graph) through vertices whose old
  * coreness is at least the smallest old coreness of an inserted endpoint start
- * from max(old, min(degree, old + n_inserted)) and are recomputed first.  Work
- * therefore follows the extent of the change rather than the graph.
+ * from max(old, min(degree, old + D, K + D)) and are recomputed first, where D is
+ * the largest number of inserted edges at one vertex and K the largest
+ * min(old(u), old(v)) over the inserted edges.  Work therefore follows the
+ * extent of the change rather than the graph.
  * Synchronises `stream` once per level of that search and as kcore_decompose does.
  */
 kcore_status kcore_update(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* prev_core,

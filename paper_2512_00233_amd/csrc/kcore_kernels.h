@@ -66,6 +66,14 @@ constexpr int kGroupRegs = 4;
 constexpr int kGroupMaxDeg = kGroupLanes * kGroupRegs;  // 64
 constexpr int kWaveRegs = 8;        // class 2: 64 lanes x 8 values
 constexpr int kWaveMaxDeg = kWave * kWaveRegs;           // 512
+// Search levels of an update run: one wavefront takes a row in slices of kBfsSlice entries; rows longer
+// than kBfsLongRow are cut into slices shared out over the whole grid.
+constexpr int kBfsSlice = 512;
+// Widest window (largest number of inserted edges at one vertex) searched by window in an update run.
+constexpr int kUpdWindowMax = 4;
+// Starting slack of a vertex that no loss of support can move (an update with insertions only).
+constexpr int32_t kSlackFinal = 1 << 30;
+constexpr int kBfsLongRow = 4096;
 constexpr int kBigBlock = 256;      // class 3: one workgroup per vertex
 constexpr int kBigRegs = 8;         // values per thread held in registers (2048 per workgroup)
 // Later rounds, optional (kcore_tuning.big_wave = 1): a first class-3 pass takes each vertex on one

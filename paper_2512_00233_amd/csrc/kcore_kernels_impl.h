@@ -1942,99 +1942,272 @@ __global__ void k_serve_reset(Ctl* ctl, int32_t r0) {
 }
 
 // ------------------------------------------------------------------ core maintenance after edge changes
-// The coreness c_old of a graph is known; edges D are removed and edges I
+// The coreness c_old of a graph is known; edges R are removed and edges I
 // inserted (the paper's future work on dynamic graphs, Sec. VI).  The run
 // restarts the same iteration from a pointwise upper bound x of the new
 // coreness c_new, with a frontier that holds every vertex whose bound may
-// exceed the h-index of its neighbours' bounds:
+// exceed the h-index of its neighbours' bounds.  Two facts about the new
+// k-core H of a vertex w (k = c_new(w)) give the bounds.  (a) In the old graph
+// H keeps every edge but the inserted ones, so with D the largest number of
+// inserted edges at one vertex every vertex of H has at least k - D neighbours
+// in H there: c_old >= c_new - D everywhere.  (b) For any level c, let S be
+// the vertices of old coreness <= c in the new (c+1)-core N.  Every component C
+// of S holds an endpoint of an inserted edge whose endpoints both lie in N:
+// otherwise every vertex of C has its c+1 neighbours in N through old edges, so
+// C together with the old (c+1)-core has minimum degree c+1 in the old graph.
 //  * removals only lower coreness, so x = c_old bounds every vertex; only the
-//    endpoints of D have a new neighbourhood;
-//  * one insertion raises coreness by at most 1, and only on vertices whose
-//    coreness equals K = min(c(u), c(v)) and that reach u or v through such
-//    vertices.  Over the batch, let T = min over I of min(c_old(u), c_old(v)).
-//    Coreness is monotone in the edge set, so a vertex w that rises also rises
-//    when only I is added, which needs c_old(w) >= T; and the component of w in
-//    the new (c_old(w)+1)-core holds an inserted edge (otherwise it was a core
-//    of the old graph) and only vertices of old coreness >= T (each either
-//    rose, or kept a coreness above c_old(w)).  So w reaches an endpoint of I
-//    in the new graph through vertices of old coreness >= T.  On the vertices
-//    so reached (the set A, found by a search from the endpoints)
-//    x = max(c_old, min(degree, c_old + |I|)); elsewhere x = c_old;
+//    endpoints of R have a new neighbourhood;
+//  * by (b) with c = c_old(w), a vertex w that rises is joined to an endpoint u
+//    of such an edge (u, v) by vertices that all rise past c_old(w) (its
+//    component of S), each of old coreness at most c_old(w) and, by (a), at
+//    least c_old(w) + 1 - D.  A vertex of old coreness below T, the smallest
+//    min(c_old(u), c_old(v)) over I, never rises (its component would hold an
+//    endpoint of old coreness below T), so w lies in the set A of vertices
+//    reached from the endpoints through vertices of old coreness >= T.  When
+//    D = 1 the component keeps to old coreness exactly c_old(w), u included,
+//    and c_old(v) >= c_old(w): u is the lower endpoint of its edge and w lies in
+//    u's subcore (reached from u through vertices of the same old coreness), the
+//    set a single insertion can raise, which the search then follows instead.
+//    A search that grows too large is given up for the superset of all
+//    vertices of old coreness >= T.  On A, x = max(c_old, min(degree, c_old + D, K_max + D)), K_max the largest
+//    min(c_old(u), c_old(v)) over I (by (a) on w and, with c = c_new(w) - 1, on
+//    the endpoints u, v); elsewhere x = c_old;
 //  * x never falls below c_old at the start (so no neighbour loses support
 //    unannounced), except on vertices left with degree <= 1, whose coreness is
 //    then known (0 or 1): they take it, and their neighbour joins the frontier.
-// Every other vertex keeps its neighbourhood and sees neighbour bounds >= c_old,
-// so its own bound is at most their h-index.  The slack of every vertex starts
-// at 0, so the first loss of support at its level activates it.
+// A vertex whose bound stays c_old and that lost no edge sees at least c_old
+// neighbours with bounds >= c_old (insertions only add neighbours), so its bound
+// is at most their h-index: the frontier is the endpoints of R, the vertices
+// whose bound rose, and the neighbours of vertices left with degree 1.  The
+// slack of every vertex starts at 0, so the first loss of support at its level
+// activates it; with insertions only, a vertex out of the frontier is final
+// (c_old <= c_new <= x = c_old) and its slack starts out of reach.
 
-// Flags (bit 0: endpoint of a removed edge, bit 1: in A) and the smallest old
-// coreness over the inserted edges' endpoints.
+// Flags (bit 0: endpoint of a removed edge, bit 1: in A, bits 2 and up: the
+// number of inserted edges at the vertex when `count` is set) and, over the
+// inserted edges, the smallest and the largest min(c_old(u), c_old(v)) and the
+// largest count: out[0], out[1] and out[2].
 __global__ __launch_bounds__(256) void k_upd_edges(const int32_t* del, int64_t nd, const int32_t* ins, int64_t ni,
-                                                   const int32_t* prev, int32_t* flag, int32_t* kmin) {
+                                                   const int32_t* prev, int32_t* flag, int32_t count, int32_t* out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int32_t m = INT32_MAX;
+  int32_t lo = INT32_MAX, hi = -1, hits = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nd + ni; i += stride) {
     if (i < nd) {
       atomicOr(&flag[del[2 * i]], 1);
       atomicOr(&flag[del[2 * i + 1]], 1);
     } else {
       const int64_t j = i - nd;
-      m = min(m, min(prev[ins[2 * j]], prev[ins[2 * j + 1]]));
+      const int32_t u = ins[2 * j], v = ins[2 * j + 1];
+      const int32_t k = min(prev[u], prev[v]);
+      lo = min(lo, k);
+      hi = max(hi, k);
+      if (count) hits = max(hits, 1 + max(atomicAdd(&flag[u], 4) >> 2, atomicAdd(&flag[v], 4) >> 2));
     }
   }
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) m = min(m, __shfl_xor(m, o));
-  if (lane_id() == 0 && m != INT32_MAX) atomicMin(kmin, m);
-}
-
-// The search for A starts from the endpoints of the inserted edges.
-__global__ __launch_bounds__(256) void k_upd_bfs_start(const int32_t* ins, int64_t ni, int32_t* flag, int32_t* queue,
-                                                       int32_t* qcnt) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * ni; i += stride) {
-    const int32_t w = ins[i];
-    if ((atomicOr(&flag[w], 2) & 2) == 0) queue[atomicAdd(qcnt, 1)] = w;
+  for (int o = 32; o >= 1; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o));
+    hi = max(hi, __shfl_xor(hi, o));
+    hits = max(hits, __shfl_xor(hits, o));
+  }
+  if (lane_id() == 0 && hi >= 0) {
+    atomicMin(&out[0], lo);
+    atomicMax(&out[1], hi);
+    atomicMax(&out[2], hits);
   }
 }
 
-// One level of the search: one wavefront per queued vertex adds its neighbours
-// whose old coreness is at least T and that are not in A yet.
+// The search for A.  With the window rule (D <= kUpdWindowMax) a search state
+// is a vertex x with a window top c in [c_old(x), c_old(x) + D - 1], encoded as
+// x | (c - c_old(x)) << 30; it moves to the neighbours y with c_old(y) in
+// [c + 1 - D, c] (state y, c), and a vertex joins A when its state of window
+// top c_old(y) is reached.  vis[y] holds one bit per window offset.  Without it
+// (the threshold rule) a state is a vertex, and it moves to the neighbours of
+// old coreness >= T.  Queues hold at most `cap` states: past it the count still
+// grows (the search is then given up) but nothing is written.
+struct UpdSearch {
+  int32_t T;      // threshold rule: smallest old coreness passed
+  int32_t D;      // window rule: window width (0: threshold rule)
+  int32_t* flag;  // bit 1: in A
+  int32_t* vis;   // window rule: reached window offsets
+  int64_t cap;    // capacity of every queue
+};
+
+constexpr uint32_t kStateMask = (1u << 30) - 1;
+
+// Vertex and window offset of a queued state (the threshold rule queues plain vertex ids).
+__device__ __forceinline__ int32_t state_vertex(const UpdSearch& q, uint32_t st) {
+  return q.D ? (int32_t)(st & kStateMask) : (int32_t)st;
+}
+__device__ __forceinline__ int32_t state_offset(const UpdSearch& q, uint32_t st) {
+  return q.D ? (int32_t)(st >> 30) : 0;
+}
+
+// Marks state (y, offset j) reached; true when it was new.  Under the window
+// rule the state of offset 0 also puts y in A.
+__device__ __forceinline__ bool upd_reach(const UpdSearch& q, int32_t y, int32_t j) {
+  if (q.D == 0) return (q.flag[y] & 2) == 0 && (atomicOr(&q.flag[y], 2) & 2) == 0;
+  const int32_t bit = 1 << j;
+  if ((q.vis[y] & bit) || (atomicOr(&q.vis[y], bit) & bit)) return false;
+  if (j == 0) atomicOr(&q.flag[y], 2);
+  return true;
+}
+
+// The search starts from the endpoints of the inserted edges: under the
+// window rule from (u, c) for c_old(u) <= c <= min(c_old(u), K) + D - 1, K the
+// edge's min(c_old(u), c_old(v)) (both endpoints lie in the new (c+1)-core).
+__global__ __launch_bounds__(256) void k_upd_bfs_start(const int32_t* ins, int64_t ni, const int32_t* prev,
+                                                       UpdSearch q, int32_t* queue, int32_t* qcnt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * ni; i += stride) {
+    const int32_t u = ins[i];
+    const int32_t lu = prev[u], k = min(lu, prev[ins[i ^ 1]]);
+    const int32_t top = q.D ? k + q.D - 1 - lu : 0;  // largest window offset of u
+    for (int32_t j = 0; j <= top; ++j)
+      if (upd_reach(q, u, j)) {
+        const int32_t pos = atomicAdd(qcnt, 1);
+        if (pos < q.cap) queue[pos] = (int32_t)((uint32_t)u | (uint32_t)j << 30);
+      }
+  }
+}
+
+// One slice of kBfsSlice entries of a row, [j0, min(j0 + kBfsSlice, e)), seen
+// from a state of window top c (threshold rule: c unused): the new states are
+// appended to out_q.  Loads, gathers and flag updates of the slice are issued
+// together, then one atomic reserves the wavefront's places in the queue.
+template <typename Off>
+__device__ __forceinline__ void bfs_slice(const int32_t* col, const int32_t* prev, const UpdSearch& q, int32_t c,
+                                          Off j0, Off e, int32_t* out_q, int32_t* out_cnt) {
+  constexpr int K = kBfsSlice / kWave;
+  const int lane = lane_id();
+  const int32_t lo = q.D ? c + 1 - q.D : q.T, hi = q.D ? c : INT32_MAX;
+  int32_t w[K], off[K];
+  bool add[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const Off j = j0 + k * kWave + lane;
+    w[k] = j < e ? col[j] : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    add[k] = false;
+    off[k] = 0;
+    if (w[k] >= 0) {
+      const int32_t cw = prev[w[k]];
+      add[k] = cw >= lo && cw <= hi;
+      off[k] = q.D ? c - cw : 0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) add[k] = add[k] && upd_reach(q, w[k], off[k]);
+  uint64_t m[K];
+  int32_t total = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    m[k] = ballot(add[k]);
+    total += popc(m[k]);
+  }
+  if (total == 0) return;
+  int32_t base = 0;
+  if (lane == 0) base = atomicAdd(out_cnt, total);
+  base = __shfl(base, 0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t pos = (int64_t)base + lanes_below(m[k]);
+    if (add[k] && pos < q.cap) out_q[pos] = (int32_t)((uint32_t)w[k] | (uint32_t)off[k] << 30);
+    base += popc(m[k]);
+  }
+}
+
+// One level of the search: one wavefront per queued state.  A row longer than
+// kBfsLongRow is only registered in long_q as (state, first slice number), the
+// row count and the slice count advancing together in one 64-bit counter so
+// that the slice numbers increase along long_q; k_upd_bfs_long then shares out
+// the slices evenly (on a skewed graph one hub row holds a large share of a
+// level's entries).  The counters rotate: this level reads cnt[0], adds to
+// cnt[1] and clears cnt[2] (the previous level's input, no longer read), and
+// clears the previous level's long-row counter.  `reached` sums the levels'
+// input counts (several levels run between two looks of the host).
 template <typename Off>
 __global__ __launch_bounds__(256) void k_upd_bfs_level(const Off* row_ptr, const int32_t* col, const int32_t* prev,
-                                                       int32_t T, int32_t* flag, const int32_t* in_q,
-                                                       const int32_t* in_cnt, int32_t* out_q, int32_t* out_cnt) {
-  const int lane = lane_id();
-  const int64_t nq = *in_cnt;
+                                                       UpdSearch q, const int32_t* in_q, const int32_t* in_cnt,
+                                                       int32_t* out_q, int32_t* out_cnt, int32_t* stale_cnt,
+                                                       int32_t* long_q, unsigned long long* long_cnt,
+                                                       unsigned long long* stale_long_cnt,
+                                                       unsigned long long* reached) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *stale_cnt = 0;
+    *stale_long_cnt = 0;
+    *reached += (unsigned long long)*in_cnt;
+  }
+  const int64_t nq = min((int64_t)*in_cnt, q.cap);
   const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
-  for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < nq; q += nw) {
-    const int32_t u = in_q[q];
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < nq; i += nw) {
+    const uint32_t st = (uint32_t)in_q[i];
+    const int32_t u = state_vertex(q, st);
     const Off b = row_ptr[u], e = row_ptr[u + 1];
-    for (Off j0 = b; j0 < e; j0 += kWave) {
-      const Off j = j0 + lane;
-      bool add = false;
-      int32_t w = 0;
-      if (j < e) {
-        w = col[j];
-        add = prev[w] >= T && (atomicOr(&flag[w], 2) & 2) == 0;
+    if (e - b > kBfsLongRow) {
+      if (lane_id() == 0) {
+        const unsigned long long slices = (unsigned long long)((e - b + kBfsSlice - 1) / kBfsSlice);
+        const unsigned long long old = atomicAdd(long_cnt, (1ull << 32) | slices);
+        const int64_t r = (int64_t)(old >> 32);
+        long_q[2 * r] = (int32_t)st;
+        long_q[2 * r + 1] = (int32_t)(old & 0xffffffffull);
       }
-      const uint64_t m = ballot(add);
-      if (!m) continue;
-      int32_t base = 0;
-      if (lane == 0) base = atomicAdd(out_cnt, popc(m));
-      base = __shfl(base, 0);
-      if (add) out_q[base + lanes_below(m)] = w;
+      continue;
     }
+    const int32_t c = prev[u] + state_offset(q, st);
+    for (Off j0 = b; j0 < e; j0 += kBfsSlice) bfs_slice(col, prev, q, c, j0, e, out_q, out_cnt);
+  }
+}
+
+// The long rows of one level: wavefront g of W takes the slices
+// [g * S / W, (g + 1) * S / W) of the S registered, finds the row of its first
+// slice by binary search over the increasing first-slice numbers, and walks on.
+template <typename Off>
+__global__ __launch_bounds__(256) void k_upd_bfs_long(const Off* row_ptr, const int32_t* col, const int32_t* prev,
+                                                      UpdSearch q, const int32_t* long_q,
+                                                      const unsigned long long* long_cnt, int32_t* out_q,
+                                                      int32_t* out_cnt) {
+  const unsigned long long lc = *long_cnt;
+  const int64_t nl = (int64_t)(lc >> 32), S = (int64_t)(lc & 0xffffffffull);
+  if (nl == 0) return;
+  const int64_t W = (int64_t)gridDim.x * blockDim.x / kWave;
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t c0 = g * S / W, c1 = (g + 1) * S / W;
+  if (c0 >= c1) return;
+  int64_t lo = 0, hi = nl - 1;  // the last row whose first slice is <= c0
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (long_q[2 * mid + 1] <= c0) lo = mid;
+    else hi = mid - 1;
+  }
+  int64_t i = lo;
+  uint32_t st = (uint32_t)long_q[2 * i];
+  int64_t first = long_q[2 * i + 1];
+  Off b = row_ptr[state_vertex(q, st)], e = row_ptr[state_vertex(q, st) + 1];
+  for (int64_t c = c0; c < c1; ++c) {
+    while (c >= first + (int64_t)((e - b + kBfsSlice - 1) / kBfsSlice)) {
+      ++i;
+      st = (uint32_t)long_q[2 * i];
+      first = long_q[2 * i + 1];
+      b = row_ptr[state_vertex(q, st)];
+      e = row_ptr[state_vertex(q, st) + 1];
+    }
+    const int32_t top = prev[state_vertex(q, st)] + state_offset(q, st);
+    bfs_slice(col, prev, q, top, b + (Off)((c - first) * kBfsSlice), e, out_q, out_cnt);
   }
 }
 
 // Start of an update run: estimates from the bounds above, classes and class
 // populations from the new degrees, no pruned lists, slack 0, and the round
-// stamp r on every frontier vertex (endpoints of removed edges, A, neighbours
-// of vertices left with degree 1); round r then builds its lists from the
-// stamps (a compaction round) as a later round.
+// stamp r on every frontier vertex (endpoints of removed edges, vertices of A
+// whose bound is above c_old, neighbours of vertices left with degree 1); round
+// r then builds its lists from the stamps (a compaction round) as a later round.
 template <typename Off>
-__global__ __launch_bounds__(256) void k_upd_init(Args<Off> a, const int32_t* prev, const int32_t* flag, int64_t ni,
-                                                  int32_t r, int32_t t0, int32_t t1, int32_t t2) {
+__global__ __launch_bounds__(256) void k_upd_init(Args<Off> a, const int32_t* prev, const int32_t* flag, int64_t rise,
+                                                  int64_t cap, int32_t all_from, int32_t insert_only, int32_t r,
+                                                  int32_t t0, int32_t t1, int32_t t2) {
   __shared__ uint32_t part[kClasses][256 / kWave];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.ctl->overflow[r % 3][0] = 1;
@@ -2049,8 +2222,11 @@ __global__ __launch_bounds__(256) void k_upd_init(Args<Off> a, const int32_t* pr
     const int32_t c = prev[v];
     const int32_t f = flag[v];
     int64_t x = c;
-    if (f & 2) x = max((int64_t)c, min((int64_t)d, (int64_t)c + ni));
-    bool seed = f != 0;
+    if ((f & 2) || c >= all_from) x = max((int64_t)c, min(min((int64_t)d, cap), (int64_t)c + rise));
+    // a vertex that kept its old coreness as its bound and lost no edge keeps at least
+    // c_old neighbours of bound >= c_old (insertions only add neighbours), so it starts
+    // out of the frontier
+    bool seed = (f & 1) || x > c;
     if (d <= 1 && x > d) {
       x = d;  // the coreness of a vertex of degree 0 or 1 is its degree
       if (d == 1) a.stamp[a.col[beg]] = r;  // its neighbour lost support it had counted
@@ -2060,7 +2236,9 @@ __global__ __launch_bounds__(256) void k_upd_init(Args<Off> a, const int32_t* pr
     a.est[v] = est_enc((int32_t)min(x, (int64_t)kEstMax), cl);
     if (cl == 2 || cl == 3) a.plen[v] = 0;
     a.cls[v] = cl;
-    a.slack[v] = 0;
+    // with insertions only, a vertex out of the frontier keeps its old coreness, which is then its
+    // new one (no bound of it lies above, none below): no loss of support can move it
+    a.slack[v] = insert_only && !seed ? kSlackFinal : 0;
     if (seed) a.stamp[v] = r;
 #pragma unroll
     for (int k = 0; k < kClasses; ++k) p[k] += cl == k;

@@ -58,7 +58,7 @@ struct Workspace {
   Ctl* host_ctl = nullptr;      // pinned
   int32_t* verr = nullptr;      // validation result (device)
   int32_t* host_verr = nullptr;  // pinned
-  int32_t* aux = nullptr;       // update runs: smallest old coreness of inserted endpoints, search counters (device)
+  int32_t* aux = nullptr;       // update runs: bounds over the inserted edges, search counters (device)
   int32_t* host_aux = nullptr;  // pinned
   int32_t* cert = nullptr;      // certificate: worst (code << 32 | vertex) as two words, then the largest core
   int32_t* host_cert = nullptr; // pinned
@@ -150,8 +150,8 @@ static kcore_status get_workspace(Workspace** out) {
     KC_HIP(hipMalloc(&ws->verr, sizeof(int32_t)));
     KC_HIP(hipHostMalloc(&ws->host_verr, sizeof(int32_t), hipHostMallocDefault));
     KC_HIP(hipHostMalloc(&ws->host_nnz, sizeof(int64_t), hipHostMallocDefault));
-    KC_HIP(hipMalloc(&ws->aux, 4 * sizeof(int32_t)));
-    KC_HIP(hipHostMalloc(&ws->host_aux, 4 * sizeof(int32_t), hipHostMallocDefault));
+    KC_HIP(hipMalloc(&ws->aux, 16 * sizeof(int32_t)));
+    KC_HIP(hipHostMalloc(&ws->host_aux, 16 * sizeof(int32_t), hipHostMallocDefault));
     KC_HIP(hipMalloc(&ws->cert, 4 * sizeof(int32_t)));
     KC_HIP(hipHostMalloc(&ws->host_cert, 4 * sizeof(int32_t), hipHostMallocDefault));
     g_ws[dev] = ws;
@@ -457,7 +457,9 @@ static float elapsed(hipEvent_t a, hipEvent_t b) {
 struct UpdateStart {
   const int32_t* prev;
   const int32_t* flag;
-  int64_t ni;
+  int64_t rise, cap;  // on A: x = max(c_old, min(degree, c_old + rise, cap))
+  int32_t all_from;   // A also holds every vertex of old coreness >= all_from (INT32_MAX: none)
+  bool insert_only;
 };
 
 // Every vertex of every graph (one graph: vbase unused) to its fixpoint.
@@ -520,8 +522,8 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   if (timing) KC_HIP(hipEventRecord(ev[0], st));
   hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, st, ws->ctl);
   if (upd) {
-    hipLaunchKernelGGL(k_upd_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, upd->prev, upd->flag, upd->ni,
-                       r0 + 1, tu.t0, tu.t1, tu.t2);
+    hipLaunchKernelGGL(k_upd_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, upd->prev, upd->flag, upd->rise,
+                       upd->cap, upd->all_from, (int32_t)upd->insert_only, r0 + 1, tu.t0, tu.t1, tu.t2);
     if (timing)
       for (int i = 1; i <= 4; ++i) KC_HIP(hipEventRecord(ev[i], st));
   } else {
@@ -966,40 +968,80 @@ static kcore_status update_impl(int64_t n, const Off* row_ptr, const int32_t* co
   int32_t* flag = ws->plow;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16));
   hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, st, flag, n, 0);
+  // aux: [0] smallest and [1] largest min(c_old(u), c_old(v)) over I, [2] D, [3..5] the search's rotating
+  // queue counters, [8..11] its two 64-bit long-row counters, [12..13] the 64-bit count of states reached
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, ws->aux, (int64_t)1, INT32_MAX);
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, ws->aux + 1, (int64_t)3, 0);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, ws->aux + 1, (int64_t)13, 0);
+  // per-vertex counts of inserted edges live in the flag word above bit 1, which holds
+  // counts below 2^29; larger batches take D = |I|
+  const bool count = ni < (1 << 28);
   if (nd + ni > 0) {
     const int egrid = (int)std::max<int64_t>(1, std::min<int64_t>((nd + ni + kBlock - 1) / kBlock,
                                                                     (int64_t)ws->num_cus * 16));
-    hipLaunchKernelGGL(k_upd_edges, dim3(egrid), dim3(kBlock), 0, st, del, nd, ins, ni, prev, flag, ws->aux);
+    hipLaunchKernelGGL(k_upd_edges, dim3(egrid), dim3(kBlock), 0, st, del, nd, ins, ni, prev, flag, (int32_t)count,
+                       ws->aux);
   }
   KC_HIP(hipGetLastError());
+  int64_t rise = 0, cap = 0;
+  int32_t all_from = INT32_MAX;
   if (ni > 0) {
-    KC_HIP(hipMemcpyAsync(ws->host_aux, ws->aux, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    KC_HIP(hipMemcpyAsync(ws->host_aux, ws->aux, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     KC_HIP(hipStreamSynchronize(st));
     const int64_t T = ws->host_aux[0];
-    // breadth-first search from the inserted endpoints through vertices of old coreness >= T;
-    // the frontier lists serve as the search queues (each vertex enters one at most once)
+    rise = count ? ws->host_aux[2] : ni;
+    cap = (int64_t)ws->host_aux[1] + rise;
+    // the window rule while D is small (window offsets fit two bits of a queue entry, ids 30 bits),
+    // otherwise the threshold rule; the slack array, not yet in use, holds the reached window offsets
+    const bool window = rise <= kUpdWindowMax && n <= (int64_t)kStateMask + 1;
+    UpdSearch q{(int32_t)T, window ? (int32_t)rise : 0, flag, ws->slack, n};
+    if (window) hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, st, ws->slack, n, 0);
+    // breadth-first search; the frontier lists serve as the search queues and the pruned-entry array,
+    // not in use before the run, as the list of long rows (two ints per row, at most
+    // kUpdWindowMax * nnz / kBfsLongRow rows)
+    int32_t* cnt = ws->aux + 3;
+    unsigned long long* lcnt = reinterpret_cast<unsigned long long*>(ws->aux + 8);
     const int sgrid = (int)std::max<int64_t>(1, std::min<int64_t>((2 * ni + kBlock - 1) / kBlock,
                                                                    (int64_t)ws->num_cus * 16));
-    hipLaunchKernelGGL(k_upd_bfs_start, dim3(sgrid), dim3(kBlock), 0, st, ins, ni, flag, ws->lists[0], ws->aux + 1);
+    hipLaunchKernelGGL(k_upd_bfs_start, dim3(sgrid), dim3(kBlock), 0, st, ins, ni, prev, q, ws->lists[0], cnt);
     KC_HIP(hipGetLastError());
-    for (int level = 0;; ++level) {
-      int32_t* cnt_in = ws->aux + 1 + (level & 1);
-      int32_t* cnt_out = ws->aux + 1 + ((level + 1) & 1);
-      KC_HIP(hipMemcpyAsync(ws->host_aux + 1, cnt_in, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-      KC_HIP(hipStreamSynchronize(st));
-      const int64_t nq = ws->host_aux[1];
-      if (nq == 0) break;
-      hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, cnt_out, (int64_t)1, 0);
-      const int lgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nq * kWave + kBlock - 1) / kBlock,
-                                                                     (int64_t)ws->num_cus * 16));
-      hipLaunchKernelGGL(k_upd_bfs_level<Off>, dim3(lgrid), dim3(kBlock), 0, st, row_ptr, col, prev, (int32_t)T,
-                         flag, ws->lists[level & 1], cnt_in, ws->lists[(level + 1) & 1], cnt_out);
+    // A search that reaches more than a sixteenth of the vertices (in states) is given up: A then also
+    // takes every vertex of old coreness >= T, a superset, since on a graph whose cores hang together the
+    // search would have reached nearly all of them at the cost of a traversal of the graph.  Levels are
+    // launched in bursts of kLevelsPerPoll on a fixed grid (each level reads its queue's length on the
+    // device); the host then reads the current queue's length and the states reached so far.  A level
+    // past the queues' capacity leaves an incomplete search behind it, but its count alone exceeds the
+    // budget, so the search is given up at the next look.
+    constexpr int kLevelsPerPoll = 4;
+    const int64_t budget = std::max<int64_t>(n / 16, 4096);
+    unsigned long long* reached = reinterpret_cast<unsigned long long*>(ws->aux + 12);
+    const int lgrid = ws->num_cus * 8;
+    for (int level = 0;;) {
+      for (int b = 0; b < kLevelsPerPoll; ++b, ++level) {
+        int32_t* cnt_in = cnt + level % 3;
+        int32_t* cnt_out = cnt + (level + 1) % 3;
+        int32_t* const qin = ws->lists[level & 1];
+        int32_t* const qout = ws->lists[(level + 1) & 1];
+        hipLaunchKernelGGL(k_upd_bfs_level<Off>, dim3(lgrid), dim3(kBlock), 0, st, row_ptr, col, prev, q, qin,
+                           cnt_in, qout, cnt_out, cnt + (level + 2) % 3, ws->pruned, lcnt + (level & 1),
+                           lcnt + ((level + 1) & 1), reached);
+        hipLaunchKernelGGL(k_upd_bfs_long<Off>, dim3(ws->num_cus * 4), dim3(kBlock), 0, st, row_ptr, col, prev, q,
+                           ws->pruned, lcnt + (level & 1), qout, cnt_out);
+      }
       KC_HIP(hipGetLastError());
+      KC_HIP(hipMemcpyAsync(ws->host_aux + 3, cnt + level % 3, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      KC_HIP(hipMemcpyAsync(ws->host_aux + 12, ws->aux + 12, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+      KC_HIP(hipStreamSynchronize(st));
+      const int64_t nq = ws->host_aux[3];
+      unsigned long long total = 0;
+      std::memcpy(&total, ws->host_aux + 12, sizeof(total));
+      if ((int64_t)total + nq > budget) {
+        all_from = (int32_t)T;
+        break;
+      }
+      if (nq == 0) break;
     }
   }
-  const UpdateStart upd{prev, flag, ni};
+  const UpdateStart upd{prev, flag, rise, cap, all_from, nd == 0};
   return run_rounds<false, Off>(ws, n, nnz, row_ptr, col, out, tu, stats, st, nullptr, &upd);
 }
 

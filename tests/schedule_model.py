@@ -51,8 +51,8 @@ def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_r
               big_first: bool = True, defer: bool = True, start=None):
     """Coreness of the graph (adjacency lists) under one random schedule; returns (estimates, rounds).
 
-    start = (estimates, frontier) begins instead from those estimates with that frontier as an ordinary
-    later round and every slack at 0 (the start of an update after edge changes)."""
+    start = (estimates, frontier[, slack]) begins instead from those estimates with that frontier as an
+    ordinary later round and the given slacks, 0 by default (the start of an update after edge changes)."""
     est = [len(adj[u]) for u in range(n)]
     big = [len(adj[u]) > big_deg for u in range(n)]
     stamp = [0] * n
@@ -62,7 +62,7 @@ def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_r
     frontier = [u for u in range(n) if est[u] >= 2]
     if start is not None:
         est = list(start[0])
-        slack = [0] * n
+        slack = list(start[2]) if len(start) > 2 else [0] * n
         first = False
         frontier = [u for u in start[1] if len(adj[u]) >= 2]
         for u in frontier:

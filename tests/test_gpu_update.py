@@ -132,6 +132,87 @@ def test_update_insertions_into_dense_cores():
         check("chung_lu mixed", g, k, k, seed=seed + 10)
 
 
+def local_insertions(g, k, seed):
+    """k new edges, each closing a triangle (a vertex joined to a neighbour of a neighbour), so that both
+    ends lie in the same dense region; returns (new graph, inserted edges)."""
+    rng = np.random.default_rng(seed)
+    e = edges_of(g)
+    existing = set(map(tuple, e.tolist()))
+    ins = set()
+    while len(ins) < k:
+        u = int(rng.integers(0, g.n))
+        nb = g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]
+        if nb.size == 0:
+            continue
+        x = int(rng.choice(nb))
+        v = int(rng.choice(g.col_idx[g.row_ptr[x]:g.row_ptr[x + 1]]))
+        a, b = min(u, v), max(u, v)
+        if a != b and (a, b) not in existing:
+            ins.add((a, b))
+    inserted = np.array(sorted(ins), np.int64).reshape(-1, 2)
+    new_e = np.concatenate([e, inserted])
+    return gg.from_edges(g.n, new_e[:, 0], new_e[:, 1]), inserted
+
+
+@pytest.mark.parametrize("name,k", [("rmat20", 1), ("rmat20", 10), ("rmat20", 300), ("rmat20", 3000),
+                                    ("road_512", 1), ("road_512", 1000), ("rmat16", 100)])
+def test_update_local_insertions(name, k):
+    # triangle-closing insertions: with one inserted edge per vertex (D = 1) the search follows the
+    # subcores of the lower endpoints, which on a skewed graph cross hub rows of many thousand entries
+    g = gg.workload(name)
+    g2, inserted = local_insertions(g, k, seed=k + 17)
+    D = int(np.bincount(inserted.ravel(), minlength=g.n).max())
+    prev = oracle.coreness(g.row_ptr, g.col_idx)
+    ref = oracle.coreness(g2.row_ptr, g2.col_idx)
+    print(f"[update] {name} +{k} local: D={D} changed={(prev != ref).sum()}", flush=True)
+    st = kc().Stats()
+    got = run_update(g2, prev, np.zeros((0, 2), np.int64), inserted, stats=st)
+    assert np.array_equal(got, ref)
+
+
+def test_update_search_keeps_to_the_touched_component():
+    # one graph made of 40 disjoint power-law parts; six insertions inside one part, with D = 1, 3 and 6:
+    # the search stays inside that part, so the run recomputes a small share of the vertices, and the
+    # result is exact
+    parts = [gg.chung_lu(5000, 2.3, 12, seed=300 + i) for i in range(40)]
+    src, dst, off = [], [], 0
+    for p in parts:
+        e = edges_of(p)
+        src.append(e[:, 0] + off)
+        dst.append(e[:, 1] + off)
+        off += p.n
+    g = gg.from_edges(off, np.concatenate(src), np.concatenate(dst))
+    prev = oracle.coreness(g.row_ptr, g.col_idx)
+    e = edges_of(g)
+    existing = set(map(tuple, e.tolist()))
+    rng = np.random.default_rng(8)
+    base = 7 * 5000  # part 7
+    # D = 1 and D = 3 take the window rule, D = 6 the threshold rule
+    for star in (1, 3, 6):
+        ins = []
+        hub = base + int(rng.integers(0, 5000))
+        while len(ins) < 6:
+            u = hub if len(ins) < star and star > 1 else base + int(rng.integers(0, 5000))
+            v = base + int(rng.integers(0, 5000))
+            a, b = min(u, v), max(u, v)
+            used = [x for pair in ins for x in pair if x != hub or star == 1]
+            if a != b and (a, b) not in existing and (a, b) not in ins and not (
+                    (a in used and a != hub) or (b in used and b != hub) or (star == 1 and hub in (a, b))):
+                ins.append((a, b))
+        inserted = np.array(ins, np.int64)
+        D = int(np.bincount(inserted.ravel(), minlength=g.n).max())
+        assert D == star, (D, star)
+        new_e = np.concatenate([e, inserted])
+        g2 = gg.from_edges(g.n, new_e[:, 0], new_e[:, 1])
+        ref = oracle.coreness(g2.row_ptr, g2.col_idx)
+        st = kc().Stats()
+        got = run_update(g2, prev, np.zeros((0, 2), np.int64), inserted, stats=st)
+        print(f"[update] 40 parts, +6 in one part (D={D}): vertex updates {st.vertex_updates} of n={g.n}",
+              flush=True)
+        assert np.array_equal(got, ref)
+        assert st.vertex_updates < g.n // 4  # a search abandoned for all of old coreness >= T would exceed it
+
+
 def test_update_time_against_full_recompute():
     # the point of an update: a small change costs far less than a full decomposition
     import time

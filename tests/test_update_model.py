@@ -43,9 +43,12 @@ def run_cases(rule, cases, seed):
         nadj, removed, inserted = random_change(rng, n, adj)
         prev = oracle.coreness(*csr(n, adj)).tolist()
         ref = oracle.coreness(*csr(n, nadj)).tolist()
-        est, frontier = um.update_start(nadj, prev, removed, inserted, rule=rule)
+        budget = rng.choice([None, None, 0, 1, 3])
+        window_max = rng.choice([4, 4, 1, 0])  # 0: always the threshold rule
+        est, frontier, slack = um.update_start(nadj, prev, removed, inserted, rule=rule, budget=budget,
+                                               window_max=window_max)
         assert all(x >= c for x, c in zip(est, ref)) or rule != "gpu", "start is not an upper bound"
-        got, _ = sm.run_model(n, nadj, rng, big_deg=rng.choice([3, 6, 100]), start=(est, frontier),
+        got, _ = sm.run_model(n, nadj, rng, big_deg=rng.choice([3, 6, 100]), start=(est, frontier, slack),
                               defer=rng.random() < 0.5, big_first=rng.random() < 0.8)
         bad += got != ref
     return bad
@@ -55,6 +58,8 @@ def test_update_start_reaches_the_new_coreness():
     assert run_cases("gpu", 1500, seed=1) == 0
 
 
-@pytest.mark.parametrize("rule", ["threshold_too_high", "endpoints_only", "clamp_to_degree", "no_neighbour_seed"])
+@pytest.mark.parametrize("rule", ["threshold_too_high", "rise_by_one", "cap_too_low", "no_removal_seed",
+                                  "window_from_upper", "window_narrow", "final_with_removals", "endpoints_only",
+                                  "clamp_to_degree", "no_neighbour_seed"])
 def test_wrong_update_starts_are_caught(rule):
     assert run_cases(rule, 3000, seed=2) > 0, rule

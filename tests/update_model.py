@@ -7,57 +7,105 @@ compare with the oracle on the changed graph:
 
 * every vertex starts at its old coreness c_old (removals only lower coreness);
 * the endpoints of removed edges start in the frontier;
-* with insertions, T = min over inserted edges of min(c_old(u), c_old(v)); the
-  vertices reached from the inserted endpoints, in the changed graph, through
-  vertices of old coreness >= T (the set A) start at
-  max(c_old, min(degree, c_old + number of insertions)) and in the frontier;
+* with insertions, T = min and K_max = max over inserted edges of
+  min(c_old(u), c_old(v)), and D = the largest number of inserted edges at one
+  vertex; the set A is found by a search in the changed graph.  While
+  D <= window_max (4 on the GPU; the window rule) its states are (vertex x, window top c) with
+  c_old(x) <= c <= c_old(x) + D - 1: it starts from (u, c) for each endpoint u
+  of an inserted edge with c <= K + D - 1 (K = the edge's min(c_old(u),
+  c_old(v))), moves to the neighbours y with c_old(y) in [c + 1 - D, c], and a
+  vertex joins A when its state of window top c_old(y) is reached (for D = 1,
+  the subcores of the lower endpoints).  Otherwise (the threshold rule) it
+  moves from the inserted endpoints through vertices of old coreness >= T.  A
+  search that reaches more than `budget` states is given up, and A is then
+  every vertex of old coreness >= T (a superset); A starts at
 * a vertex left with degree 0 or 1 starts at its degree, out of the frontier,
-  and its neighbour joins the frontier.
+  and its neighbour joins the frontier;
+* every slack starts at 0, except, when nothing was removed, on the vertices
+  out of the frontier (their old coreness is then final): SLACK_FINAL.
 
 `rule` selects deliberate mistakes that the tests must catch: "threshold_too_high"
-(T one above that minimum), "endpoints_only" (A = the inserted
+(T one above that minimum), "rise_by_one" (D taken as 1), "cap_too_low" (K_max + D - 1
+in place of K_max + D), "no_removal_seed" (removal endpoints left out of the
+frontier), "window_from_upper" (the window search started from each edge's
+upper endpoints only), "window_narrow" (windows [c + 2 - D, c]),
+"endpoints_only" (A = the inserted
 endpoints, no search), "clamp_to_degree" (removal endpoints start at
 min(c_old, degree), which drops support unannounced), "no_neighbour_seed" (a
-vertex left with degree 1 does not seed its neighbour).
+vertex left with degree 1 does not seed its neighbour), "final_with_removals"
+(the final slack given also when edges were removed).
 """
 
+SLACK_FINAL = 1 << 30
 
-def update_start(adj, prev, removed, inserted, rule: str = "gpu"):
-    """(estimates, frontier) of an update of the graph `adj` (after the changes) from coreness `prev`."""
+
+def update_start(adj, prev, removed, inserted, rule: str = "gpu", budget=None, window_max: int = 4):
+    """(estimates, frontier, slacks) of an update of the graph `adj` (after the changes) from coreness `prev`."""
     n = len(adj)
     nd, ni = len(removed), len(inserted)
     flag = [0] * n
+    all_from = float("inf")
     for u, v in removed:
         flag[u] |= 1
         flag[v] |= 1
     if ni:
         kmin = min(min(prev[u], prev[v]) for u, v in inserted)
         T = kmin + 1 if rule == "threshold_too_high" else kmin
-        queue = []
+        kmax = max(min(prev[u], prev[v]) for u, v in inserted)
+        hits = [0] * n
         for u, v in inserted:
-            for w in (u, v):
-                if not flag[w] & 2:
-                    flag[w] |= 2
-                    queue.append(w)
+            hits[u] += 1
+            hits[v] += 1
+        D = 1 if rule == "rise_by_one" else max(hits)
+        cap = kmax + D - (1 if rule == "cap_too_low" else 0)
+        window = D <= window_max
+        seen = set()  # reached states
+        queue = []
+
+        def reach(x, j):
+            if (x, j) in seen:
+                return
+            seen.add((x, j))
+            if j == 0:
+                flag[x] |= 2
+            queue.append((x, j))
+
+        for u, v in inserted:
+            for w, o in ((u, v), (v, u)):
+                if rule == "window_from_upper" and prev[w] < prev[o]:
+                    continue
+                if window:
+                    for j in range(min(prev[w], prev[o]) + D - prev[w]):
+                        reach(w, j)
+                else:
+                    reach(w, 0)
         while queue and rule != "endpoints_only":
-            q = queue.pop()
-            for w in adj[q]:
-                if prev[w] >= T and not flag[w] & 2:
-                    flag[w] |= 2
-                    queue.append(w)
+            if budget is not None and len(seen) > budget:
+                all_from = T
+                break
+            q, j = queue.pop()
+            c = prev[q] + j
+            lo = (c + 1 - D + (1 if rule == "window_narrow" else 0)) if window else T
+            hi = c if window else float("inf")
+            for y in adj[q]:
+                if lo <= prev[y] <= hi:
+                    reach(y, c - prev[y] if window else 0)
     est = [0] * n
+    slack = [0] * n
     frontier = set()
     for v in range(n):
         d, c = len(adj[v]), prev[v]
-        x = max(c, min(d, c + ni)) if flag[v] & 2 else c
+        x = max(c, min(d, c + D, cap)) if flag[v] & 2 or c >= all_from else c
         if rule == "clamp_to_degree" and flag[v] & 1:
             x = min(x, d)
-        seed = flag[v] != 0
+        seed = (flag[v] & 1 and rule != "no_removal_seed") or x > c
         if d <= 1 and x > d:
             x = d
             if d == 1 and rule != "no_neighbour_seed":
                 frontier.add(adj[v][0])
         if seed and d >= 2:
             frontier.add(v)
+        elif nd == 0 or rule == "final_with_removals":
+            slack[v] = SLACK_FINAL
         est[v] = x
-    return est, sorted(frontier)
+    return est, sorted(frontier), slack
