@@ -106,6 +106,8 @@ constexpr int kPruneCompactDen = 16;  // a class-3 pruned list is compacted once
 // workgroup takes longer than a whole round elsewhere, so hubs trade a longer pruned list for fewer
 // rescans (rmat24: 24.9 ms against 25.3 ms with the h - h/4 of other lists)
 constexpr int kHubPruneDeg = 16384;
+// Class-3 vertices above this degree sit out the first round (their first scan waits for lowered estimates).
+constexpr int kHubDelayDeg = 16384;
 
 // During a run the estimate array holds value << 2 | degree class (classes
 // 0..3; a vertex of degree <= 1 is stored as class 0, it is never activated),

@@ -1729,7 +1729,11 @@ __global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot,
   const int32_t* l3 = resid ? a.slist + f.b[3] : f.list + f.b[3];
   for (int32_t i = blockIdx.x; i < n3; i += gridDim.x) {
     const int32_t u = l3[i];
-    upd_big<BLOCK, BATCH>(a, s, u, FIRST, round, st, red, hist, stash, collect_stats != 0, resid);
+    // In the first round a vertex of degree above kHubDelayDeg is not recomputed: it keeps its degree as
+    // its bound and, like every class-3 vertex, enters the second round's frontier, where its first scan
+    // meets estimates the first round has lowered (a lower h, so a pruned list closer to its final level).
+    if (!(FIRST && kBigFirst) || uni((int32_t)(a.row_ptr[u + 1] - a.row_ptr[u])) <= kHubDelayDeg)
+      upd_big<BLOCK, BATCH>(a, s, u, FIRST, round, st, red, hist, stash, collect_stats != 0, resid);
     if (FIRST && kBigFirst) {
       // every class-3 vertex is in the second round's frontier
       int32_t self[1] = {u};

@@ -25,7 +25,9 @@ writes and atomics of all vertices of a round interleaved at random:
   was never counted at that level, and it is not updated concurrently;
 * in the first round (class-3 kernel first), a class-3 vertex notifies no
   neighbour and puts itself in the next frontier instead, and class-0..2
-  vertices skip every class-3 candidate.
+  vertices skip every class-3 candidate; a class-3 vertex of degree above
+  `delay_deg` is not even recomputed there (it keeps its degree and its
+  meaningless slack until the second round).
 
 `rule` selects deliberate mistakes, so that tests can show the model would
 notice them: "no_frontier_clause" drops the re-activation (or the deferred
@@ -48,7 +50,7 @@ def _hindex(vals, cap):
 
 
 def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_rounds: int = 10_000,
-              big_first: bool = True, defer: bool = True, start=None):
+              big_first: bool = True, defer: bool = True, start=None, delay_deg: int | None = None):
     """Coreness of the graph (adjacency lists) under one random schedule; returns (estimates, rounds).
 
     start = (estimates, frontier[, slack]) begins instead from those estimates with that frontier as an
@@ -74,6 +76,9 @@ def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_r
     def proc(u, cur_big):
         e = est[u]
         if e < 2:
+            return
+        if first and big_first and cur_big and delay_deg is not None and len(adj[u]) > delay_deg:
+            stamp[u] = r + 1  # into the second round's frontier, unrecomputed
             return
         reads = []
         for v in adj[u]:
