@@ -125,7 +125,7 @@ def counters(csvs, workload: str, commands, kernels, source_hash: str, out_json:
                     rest = [v for d, cn, v in order[k] if cn == c and d != first_id]
                     calib[c] = cal[0]
                     if rest:
-                        per["k_probe_gather (rmat24 adjacency)"][c] = (sum(rest) / len(rest), len(rest))
+                        per["k_probe_gather (the workload's adjacency)"][c] = (sum(rest) / len(rest), len(rest))
                     continue
                 per[short][c] = (sum(vals) / len(vals), len(vals))
     rows = {}
