@@ -19,6 +19,7 @@ import os
 from collections import defaultdict
 
 CALIBRATION_KERNEL_HINT = "copy"  # the calibration copy is torch's copy kernel
+XCDS, CUS = 8, 256  # MI355X: accelerator complex dies and compute units
 
 
 def _short(name: str) -> str:
@@ -142,7 +143,9 @@ def counters(csvs, workload: str, commands, kernels, source_hash: str, out_json:
         if "TCC_HIT" in c and "TCC_MISS" in c and c["TCC_HIT"] + c["TCC_MISS"] > 0:
             d["l2_hit_rate"] = round(c["TCC_HIT"] / (c["TCC_HIT"] + c["TCC_MISS"]), 4)
         if "SQ_WAVE_CYCLES" in c and "GRBM_GUI_ACTIVE" in c and c["GRBM_GUI_ACTIVE"] > 0:
-            d["mean_waves_per_cu"] = round(4 * c["SQ_WAVE_CYCLES"] / c["GRBM_GUI_ACTIVE"] / 256, 2)
+            # GRBM_GUI_ACTIVE adds up the busy cycles of the 8 XCDs (an eighth of it matches the kernel's
+            # duration at 2.4 GHz); SQ_WAVE_CYCLES counts in units of 4 cycles
+            d["mean_waves_per_cu"] = round(4 * c["SQ_WAVE_CYCLES"] / (c["GRBM_GUI_ACTIVE"] / XCDS) / CUS, 2)
         if "SQ_WAIT_INST_ANY" in c and "SQ_WAVE_CYCLES" in c and c["SQ_WAVE_CYCLES"] > 0:
             d["wait_inst_share"] = round(c["SQ_WAIT_INST_ANY"] / c["SQ_WAVE_CYCLES"], 4)
         if "SQ_WAIT_ANY" in c and "SQ_WAVE_CYCLES" in c and c["SQ_WAVE_CYCLES"] > 0:
@@ -163,7 +166,9 @@ def counters(csvs, workload: str, commands, kernels, source_hash: str, out_json:
              "Means per dispatch of rocprofv3 counters, one counter group per run (commands below; each pass is",
              "a separate process running the same bench command).  Derived: read bytes = 32, 64 and 128 times",
              "the L2-to-fabric read requests of each size; write bytes likewise; mean waves per compute unit =",
-             "4 * SQ_WAVE_CYCLES / GRBM_GUI_ACTIVE / 256; wait share = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES.", "",
+             "4 * SQ_WAVE_CYCLES / (GRBM_GUI_ACTIVE / 8) / 256 (GRBM_GUI_ACTIVE adds up the 8 XCDs' busy cycles;",
+             "an eighth of it matches the kernel's duration at 2.4 GHz); wait share = SQ_WAIT_INST_ANY /",
+             "SQ_WAVE_CYCLES.", "",
              "Commands:", "", "```", *commands, "```", ""]
     if "read_calibration" in out:
         rc = out["read_calibration"]
