@@ -171,7 +171,7 @@ def test_update_local_insertions(name, k):
 
 
 def test_update_search_keeps_to_the_touched_component():
-    # one graph made of 40 disjoint power-law parts; six insertions inside one part, with D = 1, 3 and 6:
+    # one graph made of 40 disjoint power-law parts; six insertions inside one part, with D = 1, 3, 4, 5, 6:
     # the search stays inside that part, so the run recomputes a small share of the vertices, and the
     # result is exact
     parts = [gg.chung_lu(5000, 2.3, 12, seed=300 + i) for i in range(40)]
@@ -187,8 +187,8 @@ def test_update_search_keeps_to_the_touched_component():
     existing = set(map(tuple, e.tolist()))
     rng = np.random.default_rng(8)
     base = 7 * 5000  # part 7
-    # D = 1 and D = 3 take the window rule, D = 6 the threshold rule
-    for star in (1, 3, 6):
+    # D = 1, 3 and 4 take the window rule, D = 5 and 6 the threshold rule
+    for star in (1, 3, 4, 5, 6):
         ins = []
         hub = base + int(rng.integers(0, 5000))
         while len(ins) < 6:
