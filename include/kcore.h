@@ -229,16 +229,19 @@ kcore_status kcore_decompose_noalloc(int64_t n, const int64_t* row_ptr, const in
  * otherwise it is unspecified (but memory-safe for in-range ids).  Ids must lie
  * in [0, n) (with KCORE_VALIDATE=1 the new CSR is checked, not the lists).
  * Start: removals only lower coreness, so the old coreness bounds the new one
- * and only the endpoints of removed edges are recomputed first; an insertion
- * raises coreness by at most one, only on vertices connected to its endpoints
- * through vertices of the smaller endpoint's coreness, so the vertices that
- * reach an inserted endpoint (in the new graph) through vertices whose old
- * coreness is at least the smallest old coreness of an inserted endpoint start
- * from max(old, min(degree, old + D, K + D)) and are recomputed first, where D is
- * the largest number of inserted edges at one vertex and K the largest
- * min(old(u), old(v)) over the inserted edges.  Work therefore follows the
- * extent of the change rather than the graph.
- * Synchronises `stream` once per level of that search and as kcore_decompose does.
+ * and only the endpoints of removed edges are recomputed first.  With D the
+ * largest number of inserted edges at one vertex, coreness rises by at most D,
+ * and a vertex w that rises is joined to an inserted edge, both of whose
+ * endpoints have old coreness >= old(w) + 1 - D, through vertices of old
+ * coreness in [old(w) + 1 - D, old(w)] (for D = 1: the subcore of the edge's
+ * lower endpoint).  A breadth-first search from the inserted endpoints finds
+ * the vertices so joined (while D <= 4; beyond, or past n/16 states, every
+ * vertex of old coreness >= the smallest min(old(u), old(v)) over the inserted
+ * edges); they start from max(old, min(degree, old + D, K + D)), K the largest
+ * min(old(u), old(v)), and are recomputed first if that is above old.  Work
+ * therefore follows the extent of the change rather than the graph.
+ * Synchronises `stream` once per four levels of that search and as
+ * kcore_decompose does.
  */
 kcore_status kcore_update(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* prev_core,
                           int64_t n_removed, const int32_t* removed, int64_t n_inserted, const int32_t* inserted,
