@@ -334,6 +334,18 @@ def run_serve_workload(args, torch, kc, gg, np):
     arrivals -= arrivals[0]
     progress(f"Poisson arrivals at {lam:.1f}/s")
     pois_wall, pois = serve_run(arrivals)
+    # the load sweep: the served form alone at other fractions of capacity (the FIFO baseline is run at
+    # the main load only)
+    sweep = []
+    for load in args.load_sweep:
+        lam_s = load * capacity
+        arr = np.cumsum(np.random.default_rng(int(load * 1000) + 7).exponential(1.0 / lam_s, N))
+        arr -= arr[0]
+        progress(f"load sweep: Poisson arrivals at {load} x capacity ({lam_s:.1f}/s)")
+        _, ps = serve_run(arr)
+        sweep.append({"load": load, "arrival_rate": round(lam_s, 2), "graphs_per_s": round(ps["graphs_per_s"], 2),
+                      "p50_ms": round(ps["p50_us"] / 1e3, 3), "p99_ms": round(ps["p99_us"] / 1e3, 3),
+                      "max_ms": round(ps["max_us"] / 1e3, 3)})
 
     # FIFO baseline: the same Poisson trace served by one plain call at a time
     progress("FIFO plain calls on the same trace")
@@ -380,6 +392,7 @@ def run_serve_workload(args, torch, kc, gg, np):
         "poisson": {"load": args.load, "arrival_rate": round(lam, 2), "graphs_per_s": round(pois["graphs_per_s"], 2),
                     "p50_ms": round(pois["p50_us"] / 1e3, 3), "p99_ms": round(pois["p99_us"] / 1e3, 3),
                     "max_ms": round(pois["max_us"] / 1e3, 3)},
+        "load_sweep": sweep,
         "fifo_plain": {"graphs_per_s": round(fifo_rate, 2), "p50_ms": round(pct(lat, 0.5) / 1e3, 3),
                        "p99_ms": round(pct(lat, 0.99) / 1e3, 3), "max_ms": round(float(lat[-1]) / 1e3, 3)},
         "speedup_vs_fifo": round(capacity / fifo_rate, 3),
@@ -468,6 +481,8 @@ def main():
     ap.add_argument("--requests", type=int, default=20000, help="requests in the serve workload")
     ap.add_argument("--pool", type=int, default=64, help="distinct graphs the serve requests sample")
     ap.add_argument("--load", type=float, default=0.7, help="serve: Poisson arrival rate / saturated capacity")
+    ap.add_argument("--load-sweep", type=lambda t: [float(x) for x in t.split(",") if x], default=[0.5, 0.9, 1.1],
+                    help="serve: further arrival rates (fractions of capacity) served without the FIFO baseline")
     ap.add_argument("--serve-budget-gb", type=int, default=64, help="serve: device arena budget (GiB)")
     ap.add_argument("--rounds-per-step", type=int, default=8, help="serve: rounds between step boundaries")
     ap.add_argument("--autotune", default="", help="batch workload: run the autotuner and save to this JSON")
@@ -580,7 +595,8 @@ def main():
                              "value": r["value"], "unit": "graphs/s",
                              "fifo_graphs_per_s": r["fifo_plain"]["graphs_per_s"],
                              "speedup_vs_fifo": r["speedup_vs_fifo"], "p50_ms": r["poisson"]["p50_ms"],
-                             "p99_ms": r["poisson"]["p99_ms"], "fifo_p99_ms": r["fifo_plain"]["p99_ms"],
+                             "p99_ms": r["poisson"]["p99_ms"], "max_ms": r["poisson"]["max_ms"],
+                             "fifo_p99_ms": r["fifo_plain"]["p99_ms"], "load_sweep": r["load_sweep"],
                              "exact": r["exact"]})
             continue
         g2, _, st2, ms2, _, pk2 = run_workload(name, args.steps, args.warmup, torch, kc, gg, 1)
