@@ -596,6 +596,7 @@ def main():
                              "fifo_graphs_per_s": r["fifo_plain"]["graphs_per_s"],
                              "speedup_vs_fifo": r["speedup_vs_fifo"], "p50_ms": r["poisson"]["p50_ms"],
                              "p99_ms": r["poisson"]["p99_ms"], "max_ms": r["poisson"]["max_ms"],
+                             "poisson_graphs_per_s": r["poisson"]["graphs_per_s"],
                              "fifo_p99_ms": r["fifo_plain"]["p99_ms"], "load_sweep": r["load_sweep"],
                              "exact": r["exact"]})
             continue
