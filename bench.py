@@ -476,7 +476,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat24",
-                    choices=["rmat24", "road", "er_small", "rmat20", "road_512", "batch", "serve"])
+                    choices=["rmat24", "road", "er_small", "rmat20", "road_512", "batch", "serve",
+                             "rmat24_unpermuted"])
     ap.add_argument("--graphs", type=int, default=2048, help="graphs in the batch workload")
     ap.add_argument("--requests", type=int, default=20000, help="requests in the serve workload")
     ap.add_argument("--pool", type=int, default=64, help="distinct graphs the serve requests sample")

@@ -237,6 +237,8 @@ WORKLOADS = {
     "er_small": dict(fn="erdos_renyi", kw=dict(n=10_000, m=50_000, seed=1)),
     "road": dict(fn="lattice", kw=dict(rows=4096, cols=4096, p=0.6, chord_prob=0.01, maxdist=8, seed=2)),
     "rmat24": dict(fn="rmat", kw=dict(scale=24, edge_factor=16, noise=0.05, relabel=True, seed=3)),
+    # the same samples without the random relabel (R-MAT's own id order: low ids carry the high degrees)
+    "rmat24_unpermuted": dict(fn="rmat", kw=dict(scale=24, edge_factor=16, noise=0.05, relabel=False, seed=3)),
     # scaled-down stand-ins of the same shapes, for fast tests
     "road_512": dict(fn="lattice", kw=dict(rows=512, cols=512, p=0.6, chord_prob=0.01, maxdist=8, seed=2)),
     "rmat16": dict(fn="rmat", kw=dict(scale=16, edge_factor=16, noise=0.05, relabel=True, seed=3)),
