@@ -291,8 +291,12 @@ def run_serve_workload(args, torch, kc, gg, np):
     budget = args.serve_budget_gb << 30
     wrong = 0
 
+    free_out = {}  # pinned result buffers of finished requests, by pool graph, for reuse
+
     def serve_run(arrivals):
-        """Submit request j at arrivals[j] (seconds from start); returns (wall_s, stats)."""
+        """Submit request j at arrivals[j] (seconds from start), with at most args.max_live requests
+        outstanding when that is set (a request due while that many are out waits for a completion);
+        returns (wall_s, stats)."""
         nonlocal wrong
         srv = kc.Server(hbm_budget_bytes=budget, max_queue=N + 16, rounds_per_step=args.rounds_per_step)
         live = {}
@@ -302,14 +306,17 @@ def run_serve_workload(args, torch, kc, gg, np):
             nonlocal wrong
             for c in srv.poll(1024):
                 j, out = live.pop(c.req_id)
-                if c.status != 0 or not np.array_equal(out.numpy(), refs[which[j]]):
+                g = int(which[j])
+                if c.status != 0 or not np.array_equal(out.numpy(), refs[g]):
                     wrong += 1
+                free_out.setdefault(g, []).append(out)
 
         for j in range(N):
-            while time.perf_counter() - start < arrivals[j]:
+            while time.perf_counter() - start < arrivals[j] or (args.max_live and len(live) >= args.max_live):
                 drain()
             g = int(which[j])
-            out = torch.empty(pool[g].n, dtype=torch.int32, pin_memory=True)
+            bufs = free_out.get(g)
+            out = bufs.pop() if bufs else torch.empty(pool[g].n, dtype=torch.int32, pin_memory=True)
             rid = srv.submit(pinned[g][0], pinned[g][1], out)
             live[rid] = (j, out)
         while live:
@@ -481,6 +488,9 @@ def main():
     ap.add_argument("--graphs", type=int, default=2048, help="graphs in the batch workload")
     ap.add_argument("--requests", type=int, default=20000, help="requests in the serve workload")
     ap.add_argument("--pool", type=int, default=64, help="distinct graphs the serve requests sample")
+    ap.add_argument("--max-live", type=int, default=0,
+                    help="serve: most requests outstanding at once, 0 for no bound (a bound caps the pinned result "
+                         "buffers, at the cost of result checks in the submitting loop)")
     ap.add_argument("--load", type=float, default=0.7, help="serve: Poisson arrival rate / saturated capacity")
     ap.add_argument("--load-sweep", type=lambda t: [float(x) for x in t.split(",") if x], default=[0.5, 0.9, 1.1],
                     help="serve: further arrival rates (fractions of capacity) served without the FIFO baseline")
