@@ -553,7 +553,8 @@ def main():
     roofline = roofline_of(per_kernel, args.workload, kc, runs)
     kernels = {kc.KERNEL_SYMBOLS[k]: {"ms_per_run": round(v["ms"] / runs, 4),
                                       "launches_per_run": v["launches"] // runs,
-                                      "algorithmic_gb_per_run": round(v["bytes"] / runs / 1e9, 4)}
+                                      "algorithmic_gb_per_run": round(v["bytes"] / runs / 1e9, 4),
+                                      "edge_visits_per_s": round(v["visits"] / (v["ms"] * 1e-3), 1) if v["ms"] else 0}
                for k, v in per_kernel.items() if not k.startswith("_")}
 
     result = {
