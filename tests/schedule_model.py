@@ -35,7 +35,8 @@ check) of same-kernel frontier vertices, "defer_strict_level" defers the check
 but leaves out a level equal to e (a drop from e itself), "no_kernel_order" runs both classes interleaved while
 keeping the rule that relies on their order, "skip_in_class3_kernel" applies
 the class-3 skip inside the class-3 kernel too, where such a candidate may be
-updated concurrently.
+updated concurrently, "delay_unqueued" leaves a vertex that sits out the first
+round out of the second round's frontier.
 """
 import random
 
@@ -78,7 +79,8 @@ def run_model(n, adj, rng: random.Random, big_deg: int, rule: str = "gpu", max_r
         if e < 2:
             return
         if first and big_first and cur_big and delay_deg is not None and len(adj[u]) > delay_deg:
-            stamp[u] = r + 1  # into the second round's frontier, unrecomputed
+            if rule != "delay_unqueued":
+                stamp[u] = r + 1  # into the second round's frontier, unrecomputed
             return
         reads = []
         for v in adj[u]:

@@ -36,12 +36,18 @@ def test_model_reaches_the_coreness_under_random_schedules(big_first, defer):
 
 
 def test_model_with_hubs_out_of_the_first_round():
-    # class-3 vertices above a degree bound skip the first round's recomputation: still exact
+    # class-3 vertices above a degree bound skip the first round's recomputation: still exact, and
+    # forgetting to queue them for the second round is caught
     rng = random.Random(13)
+    wrong = 0
     for n, adj, ref in CASES:
         big_deg = rng.randint(1, 6)
-        got, _ = run_model(n, adj, rng, big_deg, delay_deg=rng.randint(big_deg, 10), defer=rng.random() < 0.7)
+        delay = rng.randint(big_deg, 10)
+        got, _ = run_model(n, adj, rng, big_deg, delay_deg=delay, defer=rng.random() < 0.7)
         assert got == ref, (n, adj, big_deg)
+        bad, _ = run_model(n, adj, rng, big_deg, delay_deg=delay, rule="delay_unqueued")
+        wrong += bad != ref
+    assert wrong > 0
 
 
 @pytest.mark.parametrize("rule", ["no_frontier_clause", "no_kernel_order", "skip_in_class3_kernel", "defer_strict_level"])
