@@ -246,6 +246,10 @@ kcore_status kcore_decompose_noalloc(int64_t n, const int64_t* row_ptr, const in
 kcore_status kcore_update(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* prev_core,
                           int64_t n_removed, const int32_t* removed, int64_t n_inserted, const int32_t* inserted,
                           int32_t* out_core, const kcore_tuning* tuning, kcore_stats* stats, void* stream);
+/* The same with int32 row offsets (row_ptr[n] < 2^31), as kcore_decompose32. */
+kcore_status kcore_update32(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* prev_core,
+                            int64_t n_removed, const int32_t* removed, int64_t n_inserted, const int32_t* inserted,
+                            int32_t* out_core, const kcore_tuning* tuning, kcore_stats* stats, void* stream);
 
 /*
  * kcore_certify -- check a claimed coreness vector on the device, with no
@@ -264,6 +268,9 @@ kcore_status kcore_update(int64_t n, const int64_t* row_ptr, const int32_t* col_
  */
 kcore_status kcore_certify(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* core,
                            int32_t* out_code, int64_t* out_vertex, void* stream);
+/* The same with int32 row offsets (row_ptr[n] < 2^31). */
+kcore_status kcore_certify32(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* core,
+                             int32_t* out_code, int64_t* out_vertex, void* stream);
 
 /* One round of a run recorded by kcore_decompose_rounds. */
 typedef struct kcore_round_record {

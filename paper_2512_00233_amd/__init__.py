@@ -210,11 +210,13 @@ def load():
     lib.kcore_decompose_ex.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats), vp]
     lib.kcore_decompose_noalloc.restype = i32
     lib.kcore_decompose_noalloc.argtypes = [i64, vp, vp, vp, vp]
-    lib.kcore_certify.restype = i32
-    lib.kcore_certify.argtypes = [i64, vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i64), vp]
-    lib.kcore_update.restype = i32
-    lib.kcore_update.argtypes = [i64, vp, vp, vp, i64, vp, i64, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(Stats),
-                                 vp]
+    for name in ("kcore_certify", "kcore_certify32"):
+        getattr(lib, name).restype = i32
+        getattr(lib, name).argtypes = [i64, vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i64), vp]
+    for name in ("kcore_update", "kcore_update32"):
+        getattr(lib, name).restype = i32
+        getattr(lib, name).argtypes = [i64, vp, vp, vp, i64, vp, i64, vp, vp, ctypes.POINTER(Tuning),
+                                       ctypes.POINTER(Stats), vp]
     lib.kcore_decompose_rounds.restype = i32
     lib.kcore_decompose_rounds.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Tuning), ctypes.POINTER(RoundRecord), i32,
                                            ctypes.POINTER(i32), vp]
@@ -335,18 +337,21 @@ CERTIFY_MESSAGES = {
 
 
 def certify(row_ptr, col_idx, core, stream=None):
-    """``kcore_certify``: (code, vertex) of the local certificate of ``core`` on the device; code 0 = passes."""
+    """``kcore_certify`` (``kcore_certify32`` for int32 row offsets): (code, vertex) of the local certificate of
+    ``core`` on the device; code 0 = passes."""
     import torch
     lib = load()
-    if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32 or not (row_ptr.is_cuda and col_idx.is_cuda):
-        raise TypeError("row_ptr must be an int64 and col_idx an int32 CUDA tensor")
+    if row_ptr.dtype not in (torch.int64, torch.int32) or col_idx.dtype != torch.int32 or not (
+            row_ptr.is_cuda and col_idx.is_cuda):
+        raise TypeError("row_ptr must be an int64 or int32 and col_idx an int32 CUDA tensor")
     n = row_ptr.numel() - 1
     if core.dtype != torch.int32 or core.numel() != n or not core.is_cuda or not core.is_contiguous():
         raise ValueError("core must be a contiguous int32 CUDA tensor of n elements")
     code, vertex = ctypes.c_int32(), ctypes.c_int64()
     col_ptr = col_idx.data_ptr() if col_idx.numel() else core.data_ptr()
-    _check(lib.kcore_certify(n, row_ptr.data_ptr(), col_ptr, core.data_ptr(), ctypes.byref(code), ctypes.byref(vertex),
-                             _stream_handle(stream)))
+    fn = lib.kcore_certify if row_ptr.dtype == torch.int64 else lib.kcore_certify32
+    _check(fn(n, row_ptr.data_ptr(), col_ptr, core.data_ptr(), ctypes.byref(code), ctypes.byref(vertex),
+              _stream_handle(stream)))
     return int(code.value), int(vertex.value)
 
 
@@ -354,14 +359,16 @@ def update(row_ptr, col_idx, prev_core, removed=None, inserted=None, out=None, t
            stats: Stats | None = None, stream=None):
     """Coreness after edge changes (``kcore_update``).
 
-    row_ptr / col_idx: the graph after the changes (int64 / int32 CUDA tensors); prev_core: int32 CUDA
-    tensor [n], the coreness before; removed / inserted: int32 CUDA tensors of shape [k, 2] (or None),
-    the edges taken out and put in.  ``out`` may be ``prev_core`` itself.  Returns ``out``.
+    row_ptr / col_idx: the graph after the changes (int64 or int32 / int32 CUDA tensors; int32 offsets call
+    ``kcore_update32``); prev_core: int32 CUDA tensor [n], the coreness before; removed / inserted: int32 CUDA
+    tensors of shape [k, 2] (or None), the edges taken out and put in.  ``out`` may be ``prev_core`` itself.
+    Returns ``out``.
     """
     import torch
     lib = load()
-    if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32 or not (row_ptr.is_cuda and col_idx.is_cuda):
-        raise TypeError("row_ptr must be an int64 and col_idx an int32 CUDA tensor")
+    if row_ptr.dtype not in (torch.int64, torch.int32) or col_idx.dtype != torch.int32 or not (
+            row_ptr.is_cuda and col_idx.is_cuda):
+        raise TypeError("row_ptr must be an int64 or int32 and col_idx an int32 CUDA tensor")
     n = row_ptr.numel() - 1
     if prev_core.dtype != torch.int32 or prev_core.numel() != n or not prev_core.is_cuda or not prev_core.is_contiguous():
         raise ValueError("prev_core must be a contiguous int32 CUDA tensor of n elements")
@@ -378,10 +385,10 @@ def update(row_ptr, col_idx, prev_core, removed=None, inserted=None, out=None, t
     elif out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() or not out.is_cuda:
         raise ValueError("out must be a contiguous int32 CUDA tensor of n elements")
     col_ptr = col_idx.data_ptr() if col_idx.numel() else out.data_ptr()
-    _check(lib.kcore_update(n, row_ptr.data_ptr(), col_ptr, prev_core.data_ptr(), edges[0][0], edges[0][1],
-                            edges[1][0], edges[1][1], out.data_ptr(),
-                            ctypes.byref(tuning) if tuning is not None else None,
-                            ctypes.byref(stats) if stats is not None else None, _stream_handle(stream)))
+    fn = lib.kcore_update if row_ptr.dtype == torch.int64 else lib.kcore_update32
+    _check(fn(n, row_ptr.data_ptr(), col_ptr, prev_core.data_ptr(), edges[0][0], edges[0][1], edges[1][0],
+              edges[1][1], out.data_ptr(), ctypes.byref(tuning) if tuning is not None else None,
+              ctypes.byref(stats) if stats is not None else None, _stream_handle(stream)))
     return out
 
 

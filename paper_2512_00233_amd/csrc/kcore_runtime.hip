@@ -1468,9 +1468,21 @@ kcore_status kcore_update(int64_t n, const int64_t* row_ptr, const int32_t* col_
                               tuning, stats, (hipStream_t)stream);
 }
 
+kcore_status kcore_update32(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* prev_core,
+                            int64_t n_removed, const int32_t* removed, int64_t n_inserted, const int32_t* inserted,
+                            int32_t* out_core, const kcore_tuning* tuning, kcore_stats* stats, void* stream) {
+  return update_impl<int32_t>(n, row_ptr, col_idx, prev_core, n_removed, removed, n_inserted, inserted, out_core,
+                              tuning, stats, (hipStream_t)stream);
+}
+
 kcore_status kcore_certify(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* core,
                            int32_t* out_code, int64_t* out_vertex, void* stream) {
   return certify_impl<int64_t>(n, row_ptr, col_idx, core, out_code, out_vertex, (hipStream_t)stream);
+}
+
+kcore_status kcore_certify32(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* core,
+                             int32_t* out_code, int64_t* out_vertex, void* stream) {
+  return certify_impl<int32_t>(n, row_ptr, col_idx, core, out_code, out_vertex, (hipStream_t)stream);
 }
 
 kcore_status kcore_decompose_rounds(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t* out_core,

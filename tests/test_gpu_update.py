@@ -87,6 +87,30 @@ def test_update_tunings_and_in_place(tuning):
     check("rmat16/in place", g, 300, 300, seed=6, tuning=t, in_place=True)
 
 
+def test_update_and_certificate_with_int32_offsets():
+    # kcore_update32 / kcore_certify32: the int32-offset graph of ER small, removals and insertions
+    g = gg.workload("er_small")
+    dev = torch.device("cuda:0")
+    for n_remove, n_insert, seed in ((50, 0, 1), (0, 50, 2), (300, 300, 3)):
+        g2, removed, inserted = change(g, n_remove, n_insert, seed)
+        prev = oracle.coreness(g.row_ptr, g.col_idx)
+        ref = oracle.coreness(g2.row_ptr, g2.col_idx)
+        rp = torch.from_numpy(g2.row_ptr.astype(np.int32)).to(dev)
+        ci = torch.from_numpy(g2.col_idx).to(dev)
+        pv = torch.from_numpy(prev).to(dev)
+        rm = torch.from_numpy(removed.astype(np.int32).reshape(-1, 2)).to(dev)
+        it = torch.from_numpy(inserted.astype(np.int32).reshape(-1, 2)).to(dev)
+        got = kc().update(rp, ci, pv, rm, it)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), ref), (n_remove, n_insert)
+        assert kc().certify(rp, ci, got) == (0, -1)
+        bad = got.clone()
+        v = int(np.argmax(ref))
+        bad[v] += 1  # above its support
+        code, vertex = kc().certify(rp, ci, bad)
+        assert code != 0 and vertex <= v
+
+
 def test_update_degenerate_changes():
     # no change at all: the old coreness comes back
     g = gg.workload("road_512")
