@@ -31,12 +31,14 @@ def change(g, n_remove, n_insert, seed):
     removed = e[rem_idx]
     keep = np.ones(e.shape[0], bool)
     keep[rem_idx] = False
-    existing = set(map(tuple, e.tolist()))
     ins = set()
     while len(ins) < n_insert:
         u, v = (int(x) for x in rng.integers(0, g.n, 2))
         a, b = min(u, v), max(u, v)
-        if a != b and (a, b) not in existing and (a, b) not in ins:
+        # rows are sorted: an existing edge is found by binary search in row a
+        row = g.col_idx[g.row_ptr[a]:g.row_ptr[a + 1]]
+        j = int(np.searchsorted(row, b))
+        if a != b and not (j < row.size and row[j] == b) and (a, b) not in ins:
             ins.add((a, b))
     inserted = np.array(sorted(ins), np.int64).reshape(-1, 2)
     new_e = np.concatenate([e[keep], inserted])
@@ -85,6 +87,23 @@ def test_update_tunings_and_in_place(tuning):
     t = kc().Tuning(**tuning)
     check("rmat16", g, 300, 300, seed=5, tuning=t)
     check("rmat16/in place", g, 300, 300, seed=6, tuning=t, in_place=True)
+
+
+@pytest.mark.parametrize("name", ["rmat24", "road"])
+def test_update_at_full_size(name):
+    # the full 16.8M-vertex workloads: a mixed batch of 1,000 removals and 1,000 insertions, against the
+    # oracle on the changed graph (element by element) and the device certificate
+    g = gg.workload(name)
+    g2, removed, inserted = change(g, 1000, 1000, seed=77)
+    prev = oracle.coreness_bz(g.row_ptr, g.col_idx)
+    ref = oracle.coreness_bz(g2.row_ptr, g2.col_idx)
+    print(f"[update] {name} full size: -{len(removed)} +{len(inserted)} changed={(prev != ref).sum()}", flush=True)
+    got = run_update(g2, prev, removed, inserted)
+    assert np.array_equal(got, ref)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g2.row_ptr).to(dev)
+    ci = torch.from_numpy(g2.col_idx).to(dev)
+    assert kc().certify(rp, ci, torch.from_numpy(got).to(dev)) == (0, -1)
 
 
 def test_update_and_certificate_with_int32_offsets():
