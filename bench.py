@@ -421,12 +421,23 @@ def run_update_workload(torch, kc, gg, np, name="rmat20", seed=42):
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(seed)
     rows = []
-    for n_rem, n_ins in ((1, 0), (1000, 0), (100000, 0), (0, 1), (0, 100), (0, 1000), (1000, 1000)):
+    iso = np.flatnonzero(np.diff(g.row_ptr) == 0)
+    batches = [(1, 0, 0), (1000, 0, 0), (100000, 0, 0), (0, 1, 0), (0, 100, 0), (0, 1000, 0), (1000, 1000, 0),
+               (0, 16, 1), (0, 8, 100)]
+    for n_rem, n_ins, n_arr in batches:
         rem_idx = rng.choice(edges.shape[0], size=n_rem, replace=False)
         keep = np.ones(edges.shape[0], bool)
         keep[rem_idx] = False
         ins = set()
-        while len(ins) < n_ins:
+        if n_arr:
+            # vertex arrivals: n_arr isolated vertices join with n_ins edges each, to targets drawn in
+            # proportion to degree (random adjacency entries)
+            for z in rng.choice(iso, n_arr, replace=False):
+                targets = set()
+                while len(targets) < n_ins:
+                    targets.add(int(g.col_idx[rng.integers(0, g.col_idx.size)]))
+                ins |= {(min(int(z), t), max(int(z), t)) for t in targets}
+        while len(ins) < n_ins and not n_arr:
             u, v = (int(x) for x in rng.integers(0, g.n, 2))
             a, b = min(u, v), max(u, v)
             if a != b:
@@ -468,7 +479,7 @@ def run_update_workload(torch, kc, gg, np, name="rmat20", seed=42):
         kc.update(rp, ci, pv, rm, it, out=chk, stats=st)  # untimed: rounds and recomputations
         torch.cuda.synchronize()
         D = int(np.bincount(ins_arr.ravel(), minlength=g.n).max()) if ins_arr.size else 0
-        rows.append({"removed": int(n_rem), "inserted": int(ins_arr.shape[0]), "D": D,
+        rows.append({"removed": int(n_rem), "inserted": int(ins_arr.shape[0]), "arrivals": int(n_arr), "D": D,
                      "changed": int((ref != prev).sum()), "update_rounds": int(st.rounds),
                      "update_recomputations": int(st.vertex_updates),
                      "update_ms": round(ms_u, 4), "full_ms": round(ms_f, 4), "speedup": round(ms_f / ms_u, 2),

@@ -23,6 +23,16 @@ __device__ __forceinline__ T wave_sum(T v) {
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int32_t wave_min(int32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
 __device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
   const int lane = lane_id();
 #pragma unroll
@@ -2039,6 +2049,9 @@ struct UpdSearch {
 
 constexpr uint32_t kStateMask = (1u << 30) - 1;
 
+// A vertex of Z (two or more inserted edges, counted in its flag word from bit 2).
+__device__ __forceinline__ bool upd_heavy(int32_t f) { return (f >> 2) >= 2; }
+
 // Vertex and window offset of a queued state (the threshold rule queues plain vertex ids).
 __device__ __forceinline__ int32_t state_vertex(const UpdSearch& q, uint32_t st) {
   return q.D ? (int32_t)(st & kStateMask) : (int32_t)st;
@@ -2079,7 +2092,9 @@ __global__ __launch_bounds__(256) void k_upd_bfs_start(const int32_t* ins, int64
 // from a state of window top c (threshold rule: c unused): the new states are
 // appended to out_q.  Loads, gathers and flag updates of the slice are issued
 // together, then one atomic reserves the wavefront's places in the queue.
-template <typename Off>
+// With Src (the sources of the heavy-vertex search) every neighbour outside Z is
+// taken, at window offset 0, whatever its old coreness.
+template <bool Src = false, typename Off>
 __device__ __forceinline__ void bfs_slice(const int32_t* col, const int32_t* prev, const UpdSearch& q, int32_t c,
                                           Off j0, Off e, int32_t* out_q, int32_t* out_cnt) {
   constexpr int K = kBfsSlice / kWave;
@@ -2097,9 +2112,13 @@ __device__ __forceinline__ void bfs_slice(const int32_t* col, const int32_t* pre
     add[k] = false;
     off[k] = 0;
     if (w[k] >= 0) {
-      const int32_t cw = prev[w[k]];
-      add[k] = cw >= lo && cw <= hi;
-      off[k] = q.D ? c - cw : 0;
+      if (Src) {
+        add[k] = !upd_heavy(q.flag[w[k]]);
+      } else {
+        const int32_t cw = prev[w[k]];
+        add[k] = cw >= lo && cw <= hi;
+        off[k] = q.D ? c - cw : 0;
+      }
     }
   }
 #pragma unroll
@@ -2165,15 +2184,15 @@ __global__ __launch_bounds__(256) void k_upd_bfs_level(const Off* row_ptr, const
   }
 }
 
-// The long rows of one level: wavefront g of W takes the slices
-// [g * S / W, (g + 1) * S / W) of the S registered, finds the row of its first
-// slice by binary search over the increasing first-slice numbers, and walks on.
-template <typename Off>
-__global__ __launch_bounds__(256) void k_upd_bfs_long(const Off* row_ptr, const int32_t* col, const int32_t* prev,
-                                                      UpdSearch q, const int32_t* long_q,
-                                                      const unsigned long long* long_cnt, int32_t* out_q,
-                                                      int32_t* out_cnt) {
-  const unsigned long long lc = *long_cnt;
+// Slices of the rows registered in long_q as (state, first slice number), the
+// first slice numbers increasing along the list (lc: row count in the high 32
+// bits, slice count S in the low ones), shared out evenly: wavefront g of W
+// takes the slices [g * S / W, (g + 1) * S / W), finds the row of its first
+// slice by binary search, and walks on, calling f(state, first entry, row end)
+// on each slice.
+template <typename Off, typename F>
+__device__ __forceinline__ void for_long_slices(const Off* row_ptr, const UpdSearch& q, const int32_t* long_q,
+                                                unsigned long long lc, F&& f) {
   const int64_t nl = (int64_t)(lc >> 32), S = (int64_t)(lc & 0xffffffffull);
   if (nl == 0) return;
   const int64_t W = (int64_t)gridDim.x * blockDim.x / kWave;
@@ -2198,9 +2217,127 @@ __global__ __launch_bounds__(256) void k_upd_bfs_long(const Off* row_ptr, const 
       b = row_ptr[state_vertex(q, st)];
       e = row_ptr[state_vertex(q, st) + 1];
     }
-    const int32_t top = prev[state_vertex(q, st)] + state_offset(q, st);
-    bfs_slice(col, prev, q, top, b + (Off)((c - first) * kBfsSlice), e, out_q, out_cnt);
+    f(st, b + (Off)((c - first) * kBfsSlice), e);
   }
+}
+
+// The long rows of one level.
+template <typename Off>
+__global__ __launch_bounds__(256) void k_upd_bfs_long(const Off* row_ptr, const int32_t* col, const int32_t* prev,
+                                                      UpdSearch q, const int32_t* long_q,
+                                                      const unsigned long long* long_cnt, int32_t* out_q,
+                                                      int32_t* out_cnt) {
+  for_long_slices(row_ptr, q, long_q, *long_cnt, [&](uint32_t st, Off j0, Off e) {
+    bfs_slice(col, prev, q, prev[state_vertex(q, st)] + state_offset(q, st), j0, e, out_q, out_cnt);
+  });
+}
+
+// The heavy-vertex rule (several inserted edges at few vertices, as when a
+// vertex arrives with its edges).  Z is the set of vertices with two or more
+// inserted edges and D' the largest, over the vertices outside Z, of their
+// edges to Z plus their inserted edges to vertices outside Z.  When D' <= 1, let
+// H be the new k-core of a vertex w outside Z: in the old graph H minus Z loses
+// at most D' <= 1 neighbours per vertex (its edges to Z and its inserted edges),
+// so c_old(w) >= c_new(w) - 1.  If w rises (c = c_old(w), N the new
+// (c+1)-core), its component C among the vertices of N outside Z of old
+// coreness <= c all have old coreness exactly c, and some vertex of C has a
+// neighbour in Z or an inserted edge to a vertex of N outside Z (else C with the
+// old (c+1)-core would have minimum degree c + 1 in the old graph); that edge's
+// other endpoint lies in C or has old coreness above c, so the vertex is a lower
+// (or equal) endpoint.  The search therefore starts from the neighbours of Z
+// outside Z and the lower endpoints of the inserted edges outside Z, keeps to
+// old shells (the window rule with width 1) and never enters Z; Z is in A with
+// rise D, every other vertex rises by at most 1, and a search given up takes the
+// vertices of old coreness >= T', the smallest old coreness of a source.
+// Membership of Z is read from the counts that k_upd_edges leaves in the flags
+// (upd_heavy); the counts of D' go to bits 8 and up of vis[y] (the window bits are 0..3),
+// saturating near 2, since only whether a count exceeds 1 matters.
+
+// One more count at y (outside Z); returns the count, or 2 once it is past 1.
+__device__ __forceinline__ int32_t upd_zcount(int32_t* vis, int32_t y) {
+  if ((vis[y] >> 8) >= 2) return 2;
+  return (atomicAdd(&vis[y], 256) >> 8) + 1;
+}
+
+// Registers the rows of Z once each (claimed through bit 7 of vis) as long rows
+// in long_q for for_long_slices, and resets out[6] (D') and out[7] (T').
+template <typename Off>
+__global__ __launch_bounds__(256) void k_upd_zreg(const Off* row_ptr, const int32_t* ins, int64_t ni,
+                                                  const int32_t* flag, int32_t* vis, int32_t* long_q,
+                                                  unsigned long long* long_cnt, int32_t* out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    out[6] = 0;
+    out[7] = INT32_MAX;
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * ni; i += stride) {
+    const int32_t z = ins[i];
+    if (!upd_heavy(flag[z]) || (atomicOr(&vis[z], 128) & 128)) continue;
+    const unsigned long long slices =
+        (unsigned long long)((row_ptr[z + 1] - row_ptr[z] + kBfsSlice - 1) / kBfsSlice);
+    const unsigned long long old = atomicAdd(long_cnt, (1ull << 32) | slices);
+    const int64_t r = (int64_t)(old >> 32);
+    long_q[2 * r] = z;
+    long_q[2 * r + 1] = (int32_t)(old & 0xffffffffull);
+  }
+}
+
+// D' and T' (out[6], out[7]), and in out[14] the number of distinct neighbours
+// of Z outside Z: the rows of Z, then the inserted edges outside Z.
+template <typename Off>
+__global__ __launch_bounds__(256) void k_upd_zcount(const Off* row_ptr, const int32_t* col, const int32_t* prev,
+                                                    UpdSearch q, const int32_t* ins, int64_t ni,
+                                                    const int32_t* long_q, const unsigned long long* long_cnt,
+                                                    int32_t* out) {
+  int32_t most = 0, low = INT32_MAX, fresh = 0;
+  for_long_slices(row_ptr, q, long_q, *long_cnt, [&](uint32_t, Off j0, Off e) {
+    for (Off j = j0 + lane_id(); j < min(e, j0 + (Off)kBfsSlice); j += kWave) {
+      const int32_t y = col[j];
+      if (upd_heavy(q.flag[y])) continue;
+      const int32_t k = upd_zcount(q.vis, y);
+      most = max(most, k);
+      fresh += k == 1;
+      low = min(low, prev[y]);
+    }
+  });
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ni; i += stride) {
+    const int32_t u = ins[2 * i], v = ins[2 * i + 1];
+    if (upd_heavy(q.flag[u]) || upd_heavy(q.flag[v])) continue;
+    most = max(most, max(upd_zcount(q.vis, u), upd_zcount(q.vis, v)));
+    low = min(low, min(prev[u], prev[v]));
+  }
+  most = wave_max(most);
+  low = wave_min(low);
+  fresh = wave_sum(fresh);
+  if (lane_id() == 0) {
+    if (most) atomicMax(&out[6], most);
+    if (low != INT32_MAX) atomicMin(&out[7], low);
+    if (fresh) atomicAdd(&out[14], fresh);
+  }
+}
+
+// The sources of the heavy-vertex search: Z goes into A and is marked reached
+// (so the search never enters it), and, unless the search is given up at once
+// (sources == 0), every neighbour of Z outside Z is queued at window offset 0
+// (q.D = 1).
+template <typename Off>
+__global__ __launch_bounds__(256) void k_upd_zsrc(const Off* row_ptr, const int32_t* col, const int32_t* prev,
+                                                  UpdSearch q, const int32_t* long_q,
+                                                  const unsigned long long* long_cnt, int32_t sources,
+                                                  int32_t* queue, int32_t* qcnt) {
+  const unsigned long long lc = *long_cnt;
+  const int64_t nl = (int64_t)(lc >> 32);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += stride) {
+    const int32_t z = long_q[2 * i];
+    atomicOr(&q.vis[z], 1);
+    atomicOr(&q.flag[z], 2);
+  }
+  if (!sources) return;
+  for_long_slices(row_ptr, q, long_q, lc, [&](uint32_t, Off j0, Off e) {
+    bfs_slice<true>(col, prev, q, 0, j0, e, queue, qcnt);
+  });
 }
 
 // Start of an update run: estimates from the bounds above, classes and class
@@ -2210,8 +2347,8 @@ __global__ __launch_bounds__(256) void k_upd_bfs_long(const Off* row_ptr, const 
 // r then builds its lists from the stamps (a compaction round) as a later round.
 template <typename Off>
 __global__ __launch_bounds__(256) void k_upd_init(Args<Off> a, const int32_t* prev, const int32_t* flag, int64_t rise,
-                                                  int64_t cap, int32_t all_from, int32_t insert_only, int32_t r,
-                                                  int32_t t0, int32_t t1, int32_t t2) {
+                                                  int32_t heavy, int64_t cap, int32_t all_from, int32_t insert_only,
+                                                  int32_t r, int32_t t0, int32_t t1, int32_t t2) {
   __shared__ uint32_t part[kClasses][256 / kWave];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.ctl->overflow[r % 3][0] = 1;
@@ -2226,7 +2363,9 @@ __global__ __launch_bounds__(256) void k_upd_init(Args<Off> a, const int32_t* pr
     const int32_t c = prev[v];
     const int32_t f = flag[v];
     int64_t x = c;
-    if ((f & 2) || c >= all_from) x = max((int64_t)c, min(min((int64_t)d, cap), (int64_t)c + rise));
+    // under the heavy-vertex rule only the vertices of Z rise by more than 1
+    const int64_t up = heavy && !upd_heavy(f) ? 1 : rise;
+    if ((f & 2) || c >= all_from) x = max((int64_t)c, min(min((int64_t)d, cap), (int64_t)c + up));
     // a vertex that kept its old coreness as its bound and lost no edge keeps at least
     // c_old neighbours of bound >= c_old (insertions only add neighbours), so it starts
     // out of the frontier

@@ -458,6 +458,7 @@ struct UpdateStart {
   const int32_t* prev;
   const int32_t* flag;
   int64_t rise, cap;  // on A: x = max(c_old, min(degree, c_old + rise, cap))
+  bool heavy;         // the heavy-vertex rule: rise 1 outside Z
   int32_t all_from;   // A also holds every vertex of old coreness >= all_from (INT32_MAX: none)
   bool insert_only;
 };
@@ -523,7 +524,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, st, ws->ctl);
   if (upd) {
     hipLaunchKernelGGL(k_upd_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, upd->prev, upd->flag, upd->rise,
-                       upd->cap, upd->all_from, (int32_t)upd->insert_only, r0 + 1, tu.t0, tu.t1, tu.t2);
+                       (int32_t)upd->heavy, upd->cap, upd->all_from, (int32_t)upd->insert_only, r0 + 1, tu.t0, tu.t1, tu.t2);
     if (timing)
       for (int i = 1; i <= 4; ++i) KC_HIP(hipEventRecord(ev[i], st));
   } else {
@@ -969,9 +970,10 @@ static kcore_status update_impl(int64_t n, const Off* row_ptr, const int32_t* co
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ws->num_cus * 16));
   hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, st, flag, n, 0);
   // aux: [0] smallest and [1] largest min(c_old(u), c_old(v)) over I, [2] D, [3..5] the search's rotating
-  // queue counters, [8..11] its two 64-bit long-row counters, [12..13] the 64-bit count of states reached
+  // queue counters, [6] D' and [7] T' of the heavy-vertex rule, [8..11] the search's two 64-bit long-row
+  // counters, [12..13] the 64-bit count of states reached, [14] the number of neighbours of Z
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, ws->aux, (int64_t)1, INT32_MAX);
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, ws->aux + 1, (int64_t)13, 0);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, ws->aux + 1, (int64_t)15, 0);
   // per-vertex counts of inserted edges live in the flag word above bit 1, which holds
   // counts below 2^29; larger batches take D = |I|
   const bool count = ni < (1 << 28);
@@ -984,64 +986,96 @@ static kcore_status update_impl(int64_t n, const Off* row_ptr, const int32_t* co
   KC_HIP(hipGetLastError());
   int64_t rise = 0, cap = 0;
   int32_t all_from = INT32_MAX;
+  bool heavy = false;
   if (ni > 0) {
     KC_HIP(hipMemcpyAsync(ws->host_aux, ws->aux, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     KC_HIP(hipStreamSynchronize(st));
-    const int64_t T = ws->host_aux[0];
+    int64_t T = ws->host_aux[0];
     rise = count ? ws->host_aux[2] : ni;
     cap = (int64_t)ws->host_aux[1] + rise;
     // the window rule while D is small (window offsets fit two bits of a queue entry, ids 30 bits),
     // otherwise the threshold rule; the slack array, not yet in use, holds the reached window offsets
+    // (and, for the heavy-vertex rule, its counts)
     const bool window = rise <= kUpdWindowMax && n <= (int64_t)kStateMask + 1;
-    UpdSearch q{(int32_t)T, window ? (int32_t)rise : 0, flag, ws->slack, n};
-    if (window) hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, st, ws->slack, n, 0);
+    int32_t* vis = ws->slack;
+    if (window || rise >= 2) hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, st, vis, n, 0);
     // breadth-first search; the frontier lists serve as the search queues and the pruned-entry array,
     // not in use before the run, as the list of long rows (two ints per row, at most
-    // kUpdWindowMax * nnz / kBfsLongRow rows)
+    // kUpdWindowMax * nnz / kBfsLongRow rows; the rows of Z: at most |I| <= nnz / 2)
     int32_t* cnt = ws->aux + 3;
     unsigned long long* lcnt = reinterpret_cast<unsigned long long*>(ws->aux + 8);
     const int sgrid = (int)std::max<int64_t>(1, std::min<int64_t>((2 * ni + kBlock - 1) / kBlock,
                                                                    (int64_t)ws->num_cus * 16));
-    hipLaunchKernelGGL(k_upd_bfs_start, dim3(sgrid), dim3(kBlock), 0, st, ins, ni, prev, q, ws->lists[0], cnt);
-    KC_HIP(hipGetLastError());
-    // A search that reaches more than a sixteenth of the vertices (in states) is given up: A then also
-    // takes every vertex of old coreness >= T, a superset, since on a graph whose cores hang together the
-    // search would have reached nearly all of them at the cost of a traversal of the graph.  Levels are
-    // launched in bursts of kLevelsPerPoll on a fixed grid (each level reads its queue's length on the
-    // device); the host then reads the current queue's length and the states reached so far.  A level
-    // past the queues' capacity leaves an incomplete search behind it, but its count alone exceeds the
-    // budget, so the search is given up at the next look.
+    const int lgrid = ws->num_cus * 8;
     constexpr int kLevelsPerPoll = 4;
     const int64_t budget = std::max<int64_t>(n / 16, 4096);
-    unsigned long long* reached = reinterpret_cast<unsigned long long*>(ws->aux + 12);
-    const int lgrid = ws->num_cus * 8;
-    for (int level = 0;;) {
-      for (int b = 0; b < kLevelsPerPoll; ++b, ++level) {
-        int32_t* cnt_in = cnt + level % 3;
-        int32_t* cnt_out = cnt + (level + 1) % 3;
-        int32_t* const qin = ws->lists[level & 1];
-        int32_t* const qout = ws->lists[(level + 1) & 1];
-        hipLaunchKernelGGL(k_upd_bfs_level<Off>, dim3(lgrid), dim3(kBlock), 0, st, row_ptr, col, prev, q, qin,
-                           cnt_in, qout, cnt_out, cnt + (level + 2) % 3, ws->pruned, lcnt + (level & 1),
-                           lcnt + ((level + 1) & 1), reached);
-        hipLaunchKernelGGL(k_upd_bfs_long<Off>, dim3(ws->num_cus * 4), dim3(kBlock), 0, st, row_ptr, col, prev, q,
-                           ws->pruned, lcnt + (level & 1), qout, cnt_out);
-      }
+    bool give_up = false;
+    UpdSearch q{(int32_t)T, window ? (int32_t)rise : 0, flag, vis, n};
+    // The heavy-vertex rule, tried when some vertex has two or more inserted edges: Z's rows are
+    // registered in the second long-row list (the first level clears it), D', T' and the number of
+    // neighbours of Z are counted, and when D' <= 1 the search is the one of that rule.
+    if (count && rise >= 2 && n <= (int64_t)kStateMask + 1 && 2 * ni <= nnz) {
+      const UpdSearch zq{0, 1, flag, vis, n};
+      hipLaunchKernelGGL(k_upd_zreg<Off>, dim3(sgrid), dim3(kBlock), 0, st, row_ptr, ins, ni, flag, vis, ws->pruned,
+                         lcnt + 1, ws->aux);
+      hipLaunchKernelGGL(k_upd_zcount<Off>, dim3(lgrid), dim3(kBlock), 0, st, row_ptr, col, prev, zq, ins, ni,
+                         ws->pruned, lcnt + 1, ws->aux);
       KC_HIP(hipGetLastError());
-      KC_HIP(hipMemcpyAsync(ws->host_aux + 3, cnt + level % 3, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-      KC_HIP(hipMemcpyAsync(ws->host_aux + 12, ws->aux + 12, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+      KC_HIP(hipMemcpyAsync(ws->host_aux + 6, ws->aux + 6, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      KC_HIP(hipMemcpyAsync(ws->host_aux + 14, ws->aux + 14, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       KC_HIP(hipStreamSynchronize(st));
-      const int64_t nq = ws->host_aux[3];
-      unsigned long long total = 0;
-      std::memcpy(&total, ws->host_aux + 12, sizeof(total));
-      if ((int64_t)total + nq > budget) {
-        all_from = (int32_t)T;
-        break;
+      if (ws->host_aux[6] <= 1) {
+        heavy = true;
+        T = ws->host_aux[7];
+        q = zq;
+        // more sources than the budget allows gives the search up at once (Z still goes into A)
+        give_up = ws->host_aux[14] > budget;
+        hipLaunchKernelGGL(k_upd_zsrc<Off>, dim3(lgrid), dim3(kBlock), 0, st, row_ptr, col, prev, q, ws->pruned,
+                           lcnt + 1, (int32_t)!give_up, ws->lists[0], cnt);
       }
-      if (nq == 0) break;
+    }
+    if (give_up) {
+      all_from = (int32_t)std::min<int64_t>(T, INT32_MAX);
+    } else {
+      hipLaunchKernelGGL(k_upd_bfs_start, dim3(sgrid), dim3(kBlock), 0, st, ins, ni, prev, q, ws->lists[0], cnt);
+      KC_HIP(hipGetLastError());
+      // A search that reaches more than a sixteenth of the vertices (in states) is given up: A then also
+      // takes every vertex of old coreness >= T, a superset, since on a graph whose cores hang together
+      // the search would have reached nearly all of them at the cost of a traversal of the graph.  Levels
+      // are launched in bursts of kLevelsPerPoll on a fixed grid (each level reads its queue's length on
+      // the device); the host then reads the current queue's length and the states reached so far.  A
+      // level past the queues' capacity leaves an incomplete search behind it, but its count alone
+      // exceeds the budget, so the search is given up at the next look.
+      unsigned long long* reached = reinterpret_cast<unsigned long long*>(ws->aux + 12);
+      for (int level = 0;;) {
+        for (int b = 0; b < kLevelsPerPoll; ++b, ++level) {
+          int32_t* cnt_in = cnt + level % 3;
+          int32_t* cnt_out = cnt + (level + 1) % 3;
+          int32_t* const qin = ws->lists[level & 1];
+          int32_t* const qout = ws->lists[(level + 1) & 1];
+          hipLaunchKernelGGL(k_upd_bfs_level<Off>, dim3(lgrid), dim3(kBlock), 0, st, row_ptr, col, prev, q, qin,
+                             cnt_in, qout, cnt_out, cnt + (level + 2) % 3, ws->pruned, lcnt + (level & 1),
+                             lcnt + ((level + 1) & 1), reached);
+          hipLaunchKernelGGL(k_upd_bfs_long<Off>, dim3(ws->num_cus * 4), dim3(kBlock), 0, st, row_ptr, col, prev,
+                             q, ws->pruned, lcnt + (level & 1), qout, cnt_out);
+        }
+        KC_HIP(hipGetLastError());
+        KC_HIP(hipMemcpyAsync(ws->host_aux + 3, cnt + level % 3, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        KC_HIP(hipMemcpyAsync(ws->host_aux + 12, ws->aux + 12, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                              st));
+        KC_HIP(hipStreamSynchronize(st));
+        const int64_t nq = ws->host_aux[3];
+        unsigned long long total = 0;
+        std::memcpy(&total, ws->host_aux + 12, sizeof(total));
+        if ((int64_t)total + nq > budget) {
+          all_from = (int32_t)std::min<int64_t>(T, INT32_MAX);
+          break;
+        }
+        if (nq == 0) break;
+      }
     }
   }
-  const UpdateStart upd{prev, flag, rise, cap, all_from, nd == 0};
+  const UpdateStart upd{prev, flag, rise, cap, heavy, all_from, nd == 0};
   return run_rounds<false, Off>(ws, n, nnz, row_ptr, col, out, tu, stats, st, nullptr, &upd);
 }
 

@@ -289,3 +289,98 @@ def test_update_time_against_full_recompute():
               flush=True)
         assert np.array_equal(got, out.cpu().numpy())
         assert np.array_equal(got, oracle.coreness(g2.row_ptr, g2.col_idx))
+
+
+def arrivals(g, m, k, seed, prop=True, off=False):
+    """m vertices arrive (isolated vertices where the graph has them) with k edges each, to targets drawn in
+    proportion to degree (prop) or uniformly.  With `off`, a vertex w of the graph also gains two edges and
+    the first arrival an edge to a neighbour y of w: y, outside Z, then has two edges to Z (D' = 2).
+    Returns (new graph, inserted edges)."""
+    rng = np.random.default_rng(seed)
+    deg = np.diff(g.row_ptr)
+    iso = np.flatnonzero(deg == 0)
+    zs = [int(z) for z in (rng.choice(iso, m, replace=False) if iso.size >= m else rng.choice(g.n, m, replace=False))]
+
+    def row(x):
+        return set(g.col_idx[g.row_ptr[x]:g.row_ptr[x + 1]].tolist())
+
+    ins = set()
+    for z in zs:
+        rz, targets = row(z), set()
+        while len(targets) < k:
+            t = int(g.col_idx[rng.integers(0, g.col_idx.size)]) if prop else int(rng.integers(0, g.n))
+            if t != z and t not in rz:
+                targets.add(t)
+        ins |= {(min(z, t), max(z, t)) for t in targets}
+    if off:
+        busy = {x for pair in ins for x in pair}
+        while True:
+            w = int(g.col_idx[rng.integers(0, g.col_idx.size)])
+            y = int(rng.choice(g.col_idx[g.row_ptr[w]:g.row_ptr[w + 1]]))
+            if w not in busy and y not in busy and y not in row(zs[0]):
+                break
+        rw, extra = row(w), set()
+        while len(extra) < 2:
+            t = int(rng.integers(0, g.n))
+            if t not in rw and t not in busy and t not in (w, y):
+                extra.add(t)
+        ins |= {(min(w, t), max(w, t)) for t in extra} | {(min(zs[0], y), max(zs[0], y))}
+    inserted = np.array(sorted(ins), np.int64).reshape(-1, 2)
+    e = edges_of(g)
+    new_e = np.concatenate([e, inserted])
+    return gg.from_edges(g.n, new_e[:, 0], new_e[:, 1]), inserted
+
+
+def heavy_rule_applies(g2, inserted):
+    """D' <= 1: every vertex outside Z (two or more inserted edges) has at most one edge to Z plus inserted
+    edge to a vertex outside Z."""
+    hits = np.bincount(inserted.ravel(), minlength=g2.n)
+    z = hits >= 2
+    if not z.any():
+        return False
+    src = np.repeat(np.arange(g2.n), np.diff(g2.row_ptr))
+    cnt = np.bincount(g2.col_idx[z[src]], minlength=g2.n)
+    out = inserted[~z[inserted[:, 0]] & ~z[inserted[:, 1]]]
+    cnt += np.bincount(out.ravel(), minlength=g2.n)
+    return int(cnt[~z].max()) <= 1
+
+
+@pytest.mark.parametrize("name", ["rmat20", "road_512", "rmat16", "er_small"])
+@pytest.mark.parametrize("m,k,prop,off", [(1, 2, True, False), (1, 8, True, False), (1, 64, False, False),
+                                          (3, 8, True, False), (20, 5, False, False), (2, 4, True, True)])
+def test_update_vertex_arrivals(name, m, k, prop, off):
+    # vertices that arrive with several edges each (D = k): the heavy-vertex rule where it applies, and
+    # left off where a vertex outside Z has two edges to Z; exact either way
+    g = gg.workload(name)
+    g2, inserted = arrivals(g, m, k, seed=m * 100 + k, prop=prop, off=off)
+    prev = oracle.coreness(g.row_ptr, g.col_idx)
+    ref = oracle.coreness(g2.row_ptr, g2.col_idx)
+    rule = heavy_rule_applies(g2, inserted)
+    st = kc().Stats()
+    got = run_update(g2, prev, np.zeros((0, 2), np.int64), inserted, stats=st)
+    print(f"[update] {name}: {m} arrivals x {k} edges (prop={prop}, off={off}): heavy rule {rule}, "
+          f"changed {(prev != ref).sum()}, vertex updates {st.vertex_updates} of n={g.n}", flush=True)
+    if off:
+        assert not rule
+    assert np.array_equal(got, ref)
+    # 300 removals mixed in (edges of the old graph, or arrivals' edges, which are then not inserted)
+    g3, removed, _ = change(g2, 300, 0, seed=5)
+    key_rem = removed[:, 0] * g.n + removed[:, 1]
+    key_ins = inserted[:, 0] * g.n + inserted[:, 1]
+    got3 = run_update(g3, prev, removed[~np.isin(key_rem, key_ins)], inserted[~np.isin(key_ins, key_rem)])
+    assert np.array_equal(got3, oracle.coreness(g3.row_ptr, g3.col_idx))
+
+
+def test_update_vertex_arrival_is_local():
+    # one vertex arriving with 16 edges to high-degree vertices of R-MAT scale 20: with the heavy-vertex rule
+    # the bounds rise by 1 on the targets' shells only, so the run recomputes a small share of the vertices
+    g = gg.workload("rmat20")
+    g2, inserted = arrivals(g, 1, 16, seed=4, prop=True)
+    assert heavy_rule_applies(g2, inserted)
+    prev = oracle.coreness(g.row_ptr, g.col_idx)
+    ref = oracle.coreness(g2.row_ptr, g2.col_idx)
+    st = kc().Stats()
+    got = run_update(g2, prev, np.zeros((0, 2), np.int64), inserted, stats=st)
+    print(f"[update] rmat20, one arrival x 16: vertex updates {st.vertex_updates} of n={g.n}", flush=True)
+    assert np.array_equal(got, ref)
+    assert st.vertex_updates < g.n // 8  # D = 16 by the threshold rule would restart every vertex

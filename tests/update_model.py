@@ -19,6 +19,16 @@ compare with the oracle on the changed graph:
   moves from the inserted endpoints through vertices of old coreness >= T.  A
   search that reaches more than `budget` states is given up, and A is then
   every vertex of old coreness >= T (a superset); A starts at
+  max(c_old, min(degree, c_old + D, K_max + D)), every other vertex at c_old;
+* the heavy-vertex rule, tried first when D >= 2: Z = the vertices with two or
+  more inserted edges, D' = the largest, over the other vertices, of their edges
+  to Z plus their inserted edges to vertices outside Z.  When D' <= 1 a vertex
+  outside Z rises by at most 1 and, if it rises, shares its old shell with a
+  source: a neighbour of Z outside Z, or the lower endpoint of an inserted edge
+  outside Z.  The search then starts from the sources, keeps to old shells and
+  never enters Z; Z is in A with rise D, the rest of A with rise 1, and a
+  search given up takes the vertices of old coreness >= the smallest old
+  coreness of a source;
 * a vertex left with degree 0 or 1 starts at its degree, out of the frontier,
   and its neighbour joins the frontier;
 * every slack starts at 0, except, when nothing was removed, on the vertices
@@ -26,7 +36,10 @@ compare with the oracle on the changed graph:
 
 `rule` selects deliberate mistakes that the tests must catch: "threshold_too_high"
 (T one above that minimum), "rise_by_one" (D taken as 1), "cap_too_low" (K_max + D - 1
-in place of K_max + D), "no_removal_seed" (removal endpoints left out of the
+in place of K_max + D), "z_no_neighbour_sources" (the heavy-vertex search
+without the neighbours of Z as sources), "z_rise_one" (heavy vertices raised by
+1 only), "z_threshold_too_high" (a heavy-vertex search given up takes one shell
+too few), "no_removal_seed" (removal endpoints left out of the
 frontier), "window_from_upper" (the window search started from each edge's
 upper endpoints only), "window_narrow" (windows [c + 2 - D, c]),
 "endpoints_only" (A = the inserted
@@ -61,6 +74,29 @@ def update_start(adj, prev, removed, inserted, rule: str = "gpu", budget=None, w
         window = D <= window_max
         seen = set()  # reached states
         queue = []
+        # the heavy-vertex rule: Z = vertices with two or more inserted edges; if every other vertex has at
+        # most one edge to Z or inserted edge to a vertex outside Z (D' <= 1), a vertex outside Z rises by
+        # at most 1, the search keeps to old shells, starts from the lower endpoints of the inserted edges
+        # outside Z and from every neighbour of Z, and never enters Z; Z itself is in A
+        Z = {x for x in range(n) if hits[x] >= 2}
+        zrule = False
+        if Z and rule != "no_z_rule":
+            cnt = [0] * n
+            for z in Z:
+                for y in adj[z]:
+                    if y not in Z:
+                        cnt[y] += 1
+            for u, v in inserted:
+                if u not in Z and v not in Z:
+                    cnt[u] += 1
+                    cnt[v] += 1
+            zrule = max(cnt) <= 1
+        if zrule:
+            # a vertex outside Z that rises shares its old shell with a source, so a search given up
+            # takes the vertices of old coreness >= the smallest old coreness of a source
+            T = min([prev[y] for z in Z for y in adj[z] if y not in Z]
+                    + [min(prev[u], prev[v]) for u, v in inserted if u not in Z and v not in Z], default=T)
+            T += 1 if rule == "z_threshold_too_high" else 0
 
         def reach(x, j):
             if (x, j) in seen:
@@ -70,21 +106,40 @@ def update_start(adj, prev, removed, inserted, rule: str = "gpu", budget=None, w
                 flag[x] |= 2
             queue.append((x, j))
 
-        for u, v in inserted:
-            for w, o in ((u, v), (v, u)):
-                if rule == "window_from_upper" and prev[w] < prev[o]:
+        if zrule:
+            for z in Z:
+                flag[z] |= 2
+                if rule != "z_no_neighbour_sources":
+                    for y in adj[z]:
+                        if y not in Z:
+                            reach(y, 0)
+            for u, v in inserted:
+                if u in Z or v in Z:
                     continue
-                if window:
-                    for j in range(min(prev[w], prev[o]) + D - prev[w]):
-                        reach(w, j)
-                else:
-                    reach(w, 0)
+                for w, o in ((u, v), (v, u)):
+                    if prev[w] <= prev[o]:
+                        reach(w, 0)
+        else:
+            for u, v in inserted:
+                for w, o in ((u, v), (v, u)):
+                    if rule == "window_from_upper" and prev[w] < prev[o]:
+                        continue
+                    if window:
+                        for j in range(min(prev[w], prev[o]) + D - prev[w]):
+                            reach(w, j)
+                    else:
+                        reach(w, 0)
         while queue and rule != "endpoints_only":
             if budget is not None and len(seen) > budget:
                 all_from = T
                 break
             q, j = queue.pop()
             c = prev[q] + j
+            if zrule:
+                for y in adj[q]:
+                    if prev[y] == c and y not in Z:
+                        reach(y, 0)
+                continue
             lo = (c + 1 - D + (1 if rule == "window_narrow" else 0)) if window else T
             hi = c if window else float("inf")
             for y in adj[q]:
@@ -95,7 +150,10 @@ def update_start(adj, prev, removed, inserted, rule: str = "gpu", budget=None, w
     frontier = set()
     for v in range(n):
         d, c = len(adj[v]), prev[v]
-        x = max(c, min(d, c + D, cap)) if flag[v] & 2 or c >= all_from else c
+        rise = D if ni else 0
+        if ni and zrule:
+            rise = 1 if (v not in Z or rule == "z_rise_one") else D
+        x = max(c, min(d, c + rise, cap)) if flag[v] & 2 or c >= all_from else c
         if rule == "clamp_to_degree" and flag[v] & 1:
             x = min(x, d)
         seed = (flag[v] & 1 and rule != "no_removal_seed") or x > c
