@@ -54,6 +54,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace kcore {
@@ -69,11 +70,14 @@ constexpr int kWaveMaxDeg = kWave * kWaveRegs;           // 512
 // Search levels of an update run: one wavefront takes a row in slices of kBfsSlice entries; rows longer
 // than kBfsLongRow are cut into slices shared out over the whole grid.
 constexpr int kBfsSlice = 512;
+// Threads of the single-workgroup search kernel, and the largest level it takes (in states and entries).
+constexpr int kBfsSmallBlock = 1024;
+constexpr int kBfsSmallEntries = 8 * kBfsSmallBlock;
 // Widest window (largest number of inserted edges at one vertex) searched by window in an update run.
 constexpr int kUpdWindowMax = 4;
 // Starting slack of a vertex that no loss of support can move (an update with insertions only).
 constexpr int32_t kSlackFinal = 1 << 30;
-constexpr int kBfsLongRow = 4096;
+constexpr int kBfsLongRow = 1024;
 constexpr int kBigBlock = 256;      // class 3: one workgroup per vertex
 constexpr int kBigRegs = 8;         // values per thread held in registers (2048 per workgroup)
 // Later rounds, optional (kcore_tuning.big_wave = 1): a first class-3 pass takes each vertex on one
@@ -121,6 +125,8 @@ __host__ __device__ inline int32_t est_enc(int32_t value, int32_t cls) { return 
 __host__ __device__ inline int32_t est_val(int32_t raw) { return raw >> kEstShift; }
 __host__ __device__ inline int32_t est_cls(int32_t raw) { return raw & 3; }
 
+constexpr int kPopCopies = 32;
+
 // Control block in device memory.  Counter slot s = round % 3.
 struct Ctl {
   int32_t cnt[3][kClasses];       // sparse list sizes per class (may exceed the cap: then overflow is set)
@@ -151,7 +157,13 @@ struct Ctl {
   // deferred same-kernel checks appended in the current round, one counter per
   // buffer region (a workgroup appends to region blockIdx.x % kDeferRegions)
   int32_t dcnt[128];
+  // class counts of the initialisation kernels, summed into pop by k_pop_sum: a
+  // workgroup adds to copy blockIdx.x % kPopCopies, one 128-byte line each, since
+  // atomics from thousands of workgroups on one address are served one at a time
+  int32_t pop_part[kPopCopies][32];
 };
+// What the host reads of the control block (everything before the copies of the class counts).
+constexpr size_t kCtlHostBytes = offsetof(Ctl, pop_part);
 enum Stat {
   ST_UPDATES = 0, ST_VISITS, ST_CHANGES, ST_ACTIVATIONS, ST_PRUNE_WRITES, ST_FULL_SCANS, ST_ROUNDS,
   ST_TAIL_ROUNDS, ST_DENSE_ROUNDS

@@ -1486,8 +1486,27 @@ __global__ void k_vbase(const int64_t* graph_vtx_off, int32_t* vbase) {
   for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) vbase[v] = (int32_t)v0;
 }
 
-// est = degree, degree class, class populations (one atomic per workgroup and
-// class).  A vertex of degree <= 1 already holds its coreness and can never be
+// A workgroup's class counts (per wavefront) added to its copy of the class populations.
+__device__ __forceinline__ void add_pops(Ctl* ctl, const uint32_t (&part)[kClasses][256 / kWave]) {
+  int32_t* slot = ctl->pop_part[blockIdx.x % kPopCopies];
+#pragma unroll
+  for (int k = 0; k < kClasses; ++k) {
+    uint32_t t = 0;
+    for (int w = 0; w < 256 / kWave; ++w) t += part[k][w];
+    if (t) atomicAdd(&slot[k], (int32_t)t);
+  }
+}
+
+// The class populations: the sum of the copies (one workgroup, after the initialisation kernel).
+__global__ void k_pop_sum(Ctl* ctl) {
+  if (threadIdx.x < kClasses) {
+    int32_t t = 0;
+    for (int c = 0; c < kPopCopies; ++c) t += ctl->pop_part[c][threadIdx.x];
+    ctl->pop[threadIdx.x] = t;
+  }
+}
+
+// est = degree, degree class, class populations (by copies, see add_pops).  A vertex of degree <= 1 already holds its coreness and can never be
 // activated: it gets no class (kClasses) and no list space.  Only classes 2
 // and 3 keep pruned lists.
 template <typename Off>
@@ -1517,11 +1536,7 @@ __global__ __launch_bounds__(256) void k_init(Args<Off> a, int32_t r0, int32_t t
     if (lane_id() == 0) part[k][wave] = w;
   }
   __syncthreads();
-  if (threadIdx.x < kClasses) {
-    uint32_t t = 0;
-    for (int w = 0; w < 256 / kWave; ++w) t += part[threadIdx.x][w];
-    if (t) atomicAdd(&a.ctl->pop[threadIdx.x], (int32_t)t);
-  }
+  if (threadIdx.x == 0) add_pops(a.ctl, part);
 }
 
 // Build class lists from a per-vertex predicate: SEED = the first-round lists
@@ -2232,6 +2247,92 @@ __global__ __launch_bounds__(256) void k_upd_bfs_long(const Off* row_ptr, const 
   });
 }
 
+// Levels of the search inside one workgroup of kBfsSmallBlock threads, from
+// `level` on, while a level holds at most kBfsSmallBlock states and
+// kBfsSmallEntries adjacency entries: a search that has narrowed to a few states
+// per level (a long path through one shell) then costs no launch and no look of
+// the host per level.  A level's entries are shared out over all threads (an
+// exclusive scan of the states' degrees in LDS, each thread finding its entry's
+// state by binary search), the level's new states are counted in LDS, and stores
+// become visible to the whole workgroup at each barrier.  The queues and
+// counters rotate as in k_upd_bfs_level, `reached` grows by each level's input,
+// and the kernel stops at an empty level, at a level larger than it takes, or
+// where `reached` plus the level's input would pass `budget`; out[15] is the
+// level it stopped at.  Both long-row counters are cleared on exit, so that
+// later launches of k_upd_bfs_level start from empty lists.
+template <typename Off>
+__global__ __launch_bounds__(kBfsSmallBlock) void k_upd_bfs_small(const Off* row_ptr, const int32_t* col,
+                                                                  const int32_t* prev, UpdSearch q, int32_t* q0,
+                                                                  int32_t* q1, int32_t* cnt, int32_t level,
+                                                                  int64_t budget, unsigned long long* reached,
+                                                                  unsigned long long* long_cnt, int32_t* out) {
+  __shared__ int32_t first[kBfsSmallBlock];  // first entry of each state (of the level's entries)
+  __shared__ Off base[kBfsSmallBlock];       // its row start
+  __shared__ int32_t top[kBfsSmallBlock];    // its window top (threshold rule: unused)
+  __shared__ int32_t red[kBfsSmallBlock / kWave];
+  __shared__ int32_t made;                   // states appended in the level
+  const int tid = threadIdx.x;
+  for (;; ++level) {
+    const int32_t nin = ld_counter(&cnt[level % 3]);
+    const unsigned long long done = __hip_atomic_load(reached, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (nin == 0 || nin > kBfsSmallBlock || (int64_t)done + nin > budget) break;
+    const int32_t* in_q = (level & 1) ? q1 : q0;
+    int32_t* out_q = (level & 1) ? q0 : q1;
+    int32_t d = 0;
+    if (tid < nin) {
+      const uint32_t st = (uint32_t)in_q[tid];
+      const int32_t u = state_vertex(q, st);
+      const Off b = row_ptr[u];
+      d = (int32_t)min((Off)(kBfsSmallEntries + 1), row_ptr[u + 1] - b);  // (the sum stays in range)
+      base[tid] = b;
+      top[tid] = prev[u] + state_offset(q, st);
+    }
+    int32_t E = 0;
+    const int32_t f = block_excl_scan<kBfsSmallBlock>(d, E, red);
+    if (E > kBfsSmallEntries) break;
+    if (tid < nin) first[tid] = f;
+    if (tid == 0) {
+      made = 0;
+      cnt[(level + 2) % 3] = 0;  // the previous level's input, no longer read
+      __hip_atomic_store(reached, done + (unsigned long long)nin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    for (int32_t j0 = 0; j0 < E; j0 += kBfsSmallBlock) {
+      const int32_t j = j0 + tid;
+      int32_t w = 0, off = 0;
+      bool add = false;
+      if (j < E) {
+        int32_t lo = 0, hi = nin - 1;  // the last state whose first entry is <= j
+        while (lo < hi) {
+          const int32_t mid = (lo + hi + 1) / 2;
+          if (first[mid] <= j) lo = mid;
+          else hi = mid - 1;
+        }
+        w = col[base[lo] + (Off)(j - first[lo])];
+        const int32_t c = top[lo], cw = prev[w];
+        const bool in = q.D ? (cw >= c + 1 - q.D && cw <= c) : cw >= q.T;
+        off = q.D ? c - cw : 0;
+        add = in && upd_reach(q, w, off);
+      }
+      const uint64_t m = ballot(add);
+      if (m) {
+        int32_t pos = 0;
+        if (lane_id() == 0) pos = atomicAdd(&made, popc(m));
+        pos = __shfl(pos, 0) + lanes_below(m);
+        if (add && pos < q.cap) out_q[pos] = (int32_t)((uint32_t)w | (uint32_t)off << 30);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) cnt[(level + 1) % 3] = made;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[15] = level;
+    long_cnt[0] = 0;
+    long_cnt[1] = 0;
+  }
+}
+
 // The heavy-vertex rule (several inserted edges at few vertices, as when a
 // vertex arrives with its edges).  Z is the set of vertices with two or more
 // inserted edges and D' the largest, over the vertices outside Z, of their
@@ -2393,11 +2494,7 @@ __global__ __launch_bounds__(256) void k_upd_init(Args<Off> a, const int32_t* pr
     if (lane_id() == 0) part[k][wave] = w;
   }
   __syncthreads();
-  if (threadIdx.x < kClasses) {
-    uint32_t t = 0;
-    for (int w = 0; w < 256 / kWave; ++w) t += part[threadIdx.x][w];
-    if (t) atomicAdd(&a.ctl->pop[threadIdx.x], (int32_t)t);
-  }
+  if (threadIdx.x == 0) add_pops(a.ctl, part);
 }
 
 // ------------------------------------------------------------------ degree relabelling

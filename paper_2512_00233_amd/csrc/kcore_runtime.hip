@@ -525,10 +525,12 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   if (upd) {
     hipLaunchKernelGGL(k_upd_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, upd->prev, upd->flag, upd->rise,
                        (int32_t)upd->heavy, upd->cap, upd->all_from, (int32_t)upd->insert_only, r0 + 1, tu.t0, tu.t1, tu.t2);
+    hipLaunchKernelGGL(k_pop_sum, dim3(1), dim3(64), 0, st, ws->ctl);
     if (timing)
       for (int i = 1; i <= 4; ++i) KC_HIP(hipEventRecord(ev[i], st));
   } else {
     hipLaunchKernelGGL(k_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, r0, tu.t0, tu.t1, tu.t2);
+    hipLaunchKernelGGL(k_pop_sum, dim3(1), dim3(64), 0, st, ws->ctl);
     hipLaunchKernelGGL((k_compact<true, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, 0);
     launch_updates<true, BATCH, Off>(a, tu, 0, collect, st, timing ? ev + 1 : nullptr);
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, ws->ctl, 1);
@@ -571,7 +573,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
                  d[1][ST_ACTIVATIONS], d[1][ST_FULL_SCANS], h.stats[ST_TAIL_ROUNDS], ms);
   };
   if (timing) {
-    KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, kCtlHostBytes, hipMemcpyDeviceToHost, st));
     KC_HIP(hipStreamSynchronize(st));
     init_ms = elapsed(ev[0], ev[1]);
     kms[KCORE_K_BIG_FIRST] = kBigFirst ? elapsed(ev[1], ev[2]) : elapsed(ev[2], ev[3]);
@@ -590,7 +592,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   for (;;) {
     if (tu.max_rounds > 0) {
       if (launches >= tu.max_rounds) {
-        KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, kCtlHostBytes, hipMemcpyDeviceToHost, st));
         KC_HIP(hipStreamSynchronize(st));
         r = ws->host_ctl->rbase;
         break;
@@ -605,7 +607,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
       if (s != KCORE_OK) return s;
     }
     launches += K;
-    KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    KC_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, kCtlHostBytes, hipMemcpyDeviceToHost, st));
     KC_HIP(hipStreamSynchronize(st));
     const Ctl& h = *ws->host_ctl;
     rounds_done += (int64_t)h.rbase - r;
@@ -1008,7 +1010,8 @@ static kcore_status update_impl(int64_t n, const Off* row_ptr, const int32_t* co
                                                                    (int64_t)ws->num_cus * 16));
     const int lgrid = ws->num_cus * 8;
     constexpr int kLevelsPerPoll = 4;
-    const int64_t budget = std::max<int64_t>(n / 16, 4096);
+    // (never above n, the queues' capacity: a level that overflows a queue also passes the budget)
+    const int64_t budget = std::min<int64_t>(std::max<int64_t>(n / 16, 4096), n);
     bool give_up = false;
     UpdSearch q{(int32_t)T, window ? (int32_t)rise : 0, flag, vis, n};
     // The heavy-vertex rule, tried when some vertex has two or more inserted edges: Z's rows are
@@ -1039,32 +1042,42 @@ static kcore_status update_impl(int64_t n, const Off* row_ptr, const int32_t* co
     } else {
       hipLaunchKernelGGL(k_upd_bfs_start, dim3(sgrid), dim3(kBlock), 0, st, ins, ni, prev, q, ws->lists[0], cnt);
       KC_HIP(hipGetLastError());
-      // A search that reaches more than a sixteenth of the vertices (in states) is given up: A then also
-      // takes every vertex of old coreness >= T, a superset, since on a graph whose cores hang together
-      // the search would have reached nearly all of them at the cost of a traversal of the graph.  Levels
-      // are launched in bursts of kLevelsPerPoll on a fixed grid (each level reads its queue's length on
-      // the device); the host then reads the current queue's length and the states reached so far.  A
-      // level past the queues' capacity leaves an incomplete search behind it, but its count alone
-      // exceeds the budget, so the search is given up at the next look.
+      // A search that reaches more than a sixteenth of the vertices (in states; at least 4096, at most n)
+      // is given up: A then also takes every vertex of old coreness >= T, a superset, since on a graph
+      // whose cores hang together the search would have reached nearly all of them at the cost of a
+      // traversal of the graph.  Levels are launched in bursts of kLevelsPerPoll on a fixed grid (each
+      // level reads its queue's length on the device); the host then reads the current queue's length and
+      // the states reached so far.  A level past the queues' capacity leaves an incomplete search behind
+      // it, but its count alone exceeds the budget, so the search is given up at the next look.
+      // Levels holding at most kBfsSmallBlock states (and kBfsSmallEntries entries) run inside one
+      // workgroup (k_upd_bfs_small, which stops at a larger level); the first level is known to be small
+      // when the sources are few.
       unsigned long long* reached = reinterpret_cast<unsigned long long*>(ws->aux + 12);
+      const int64_t sources = 2 * ni * std::max<int32_t>(1, q.D) + (heavy ? ws->host_aux[14] : 0);
+      bool small = sources <= kBfsSmallBlock;
       for (int level = 0;;) {
-        for (int b = 0; b < kLevelsPerPoll; ++b, ++level) {
-          int32_t* cnt_in = cnt + level % 3;
-          int32_t* cnt_out = cnt + (level + 1) % 3;
-          int32_t* const qin = ws->lists[level & 1];
-          int32_t* const qout = ws->lists[(level + 1) & 1];
-          hipLaunchKernelGGL(k_upd_bfs_level<Off>, dim3(lgrid), dim3(kBlock), 0, st, row_ptr, col, prev, q, qin,
-                             cnt_in, qout, cnt_out, cnt + (level + 2) % 3, ws->pruned, lcnt + (level & 1),
-                             lcnt + ((level + 1) & 1), reached);
-          hipLaunchKernelGGL(k_upd_bfs_long<Off>, dim3(ws->num_cus * 4), dim3(kBlock), 0, st, row_ptr, col, prev,
-                             q, ws->pruned, lcnt + (level & 1), qout, cnt_out);
+        if (small) {
+          hipLaunchKernelGGL(k_upd_bfs_small<Off>, dim3(1), dim3(kBfsSmallBlock), 0, st, row_ptr, col, prev, q,
+                             ws->lists[0], ws->lists[1], cnt, level, budget, reached, lcnt, ws->aux);
+        } else {
+          for (int b = 0; b < kLevelsPerPoll; ++b, ++level) {
+            int32_t* cnt_in = cnt + level % 3;
+            int32_t* cnt_out = cnt + (level + 1) % 3;
+            int32_t* const qin = ws->lists[level & 1];
+            int32_t* const qout = ws->lists[(level + 1) & 1];
+            hipLaunchKernelGGL(k_upd_bfs_level<Off>, dim3(lgrid), dim3(kBlock), 0, st, row_ptr, col, prev, q, qin,
+                               cnt_in, qout, cnt_out, cnt + (level + 2) % 3, ws->pruned, lcnt + (level & 1),
+                               lcnt + ((level + 1) & 1), reached);
+            hipLaunchKernelGGL(k_upd_bfs_long<Off>, dim3(ws->num_cus * 4), dim3(kBlock), 0, st, row_ptr, col,
+                               prev, q, ws->pruned, lcnt + (level & 1), qout, cnt_out);
+          }
         }
         KC_HIP(hipGetLastError());
-        KC_HIP(hipMemcpyAsync(ws->host_aux + 3, cnt + level % 3, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        KC_HIP(hipMemcpyAsync(ws->host_aux + 12, ws->aux + 12, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                              st));
+        // aux[3..15]: the queue counters, the long-row counters, the states reached, the small kernel's level
+        KC_HIP(hipMemcpyAsync(ws->host_aux + 3, ws->aux + 3, 13 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         KC_HIP(hipStreamSynchronize(st));
-        const int64_t nq = ws->host_aux[3];
+        if (small) level = ws->host_aux[15];
+        const int64_t nq = ws->host_aux[3 + level % 3];
         unsigned long long total = 0;
         std::memcpy(&total, ws->host_aux + 12, sizeof(total));
         if ((int64_t)total + nq > budget) {
@@ -1072,6 +1085,8 @@ static kcore_status update_impl(int64_t n, const Off* row_ptr, const int32_t* co
           break;
         }
         if (nq == 0) break;
+        // a small launch that returns with a live level stopped at a large one: a burst follows
+        small = !small && nq <= kBfsSmallBlock;
       }
     }
   }
@@ -1449,7 +1464,7 @@ kcore_status serve_step(ServeArena* A, int32_t rounds, int32_t nslots, int32_t* 
     KC_HIP(hipGetLastError());
     KC_HIP(hipMemcpyAsync(host_status, A->status, sizeof(int32_t) * nslots, hipMemcpyDeviceToHost, st));
   }
-  KC_HIP(hipMemcpyAsync(host_ctl, A->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  KC_HIP(hipMemcpyAsync(host_ctl, A->ctl, kCtlHostBytes, hipMemcpyDeviceToHost, st));
   return KCORE_OK;
 }
 

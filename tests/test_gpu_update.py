@@ -384,3 +384,35 @@ def test_update_vertex_arrival_is_local():
     print(f"[update] rmat20, one arrival x 16: vertex updates {st.vertex_updates} of n={g.n}", flush=True)
     assert np.array_equal(got, ref)
     assert st.vertex_updates < g.n // 8  # D = 16 by the threshold rule would restart every vertex
+
+
+def test_update_window_search_on_small_dense_graphs():
+    # dense graphs of 12 to 80 vertices with D = 2, 3 or 4 inserted edges at one vertex (the window rule, whose
+    # states are vertex and window offset, so one level can hold more states than there are vertices) and
+    # further single insertions: exact, with the search given up where it would overflow its queues
+    rng = np.random.default_rng(21)
+    for case in range(60):
+        n = int(rng.integers(12, 81))
+        a = np.triu(rng.random((n, n)) < rng.uniform(0.3, 0.85), 1)
+        u, v = np.nonzero(a)
+        full = gg.from_edges(n, u, v)
+        e = edges_of(full)
+        D = int(rng.integers(2, 5))
+        hub = int(rng.integers(0, n))
+        at_hub = np.flatnonzero((e[:, 0] == hub) | (e[:, 1] == hub))
+        if at_hub.size < D:
+            continue
+        pick = set(rng.choice(at_hub, D, replace=False).tolist())
+        used = {hub} | {int(x) for i in pick for x in e[i]}
+        for i in rng.permutation(e.shape[0])[:40]:
+            if len(pick) >= D + 6:
+                break
+            if int(e[i, 0]) not in used and int(e[i, 1]) not in used:
+                pick.add(int(i))
+                used |= {int(e[i, 0]), int(e[i, 1])}
+        ins = np.zeros(e.shape[0], bool)
+        ins[sorted(pick)] = True
+        old = gg.from_edges(n, e[~ins, 0], e[~ins, 1])
+        prev = oracle.coreness(old.row_ptr, old.col_idx)
+        got = run_update(full, prev, np.zeros((0, 2), np.int32), e[ins])
+        assert np.array_equal(got, oracle.coreness(full.row_ptr, full.col_idx)), (case, n, D)
