@@ -238,10 +238,16 @@ kcore_status kcore_decompose_noalloc(int64_t n, const int64_t* row_ptr, const in
  * the vertices so joined (while D <= 4; beyond, or past n/16 states, every
  * vertex of old coreness >= the smallest min(old(u), old(v)) over the inserted
  * edges); they start from max(old, min(degree, old + D, K + D)), K the largest
- * min(old(u), old(v)), and are recomputed first if that is above old.  Work
- * therefore follows the extent of the change rather than the graph.
- * Synchronises `stream` once per four levels of that search and as
- * kcore_decompose does.
+ * min(old(u), old(v)), and are recomputed first if that is above old.  When D >= 2
+ * and, with Z the vertices of two or more inserted edges, no other vertex has two
+ * edges to Z and inserted edges to vertices outside Z together (as when vertices
+ * arrive with their edges), only Z may rise by more than 1: the search then
+ * keeps to the old shells of Z's neighbours and of the lower endpoints of the
+ * inserted edges outside Z, and the vertices it finds start from old + 1 (Z
+ * from old + D).  Work therefore follows the extent of the change rather than
+ * the graph.  Synchronises `stream` once or twice before the search, once per
+ * four levels of it (levels of at most 1,024 states run inside one workgroup,
+ * with one look after them), and as kcore_decompose does.
  */
 kcore_status kcore_update(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* prev_core,
                           int64_t n_removed, const int32_t* removed, int64_t n_inserted, const int32_t* inserted,
