@@ -128,13 +128,19 @@ __host__ __device__ inline int32_t est_cls(int32_t raw) { return raw & 3; }
 constexpr int kPopCopies = 32;
 
 // Control block in device memory.  Counter slot s = round % 3.
+// List counters: the counter of class k sits at index k * kCtr of its array, one
+// 128-byte line per class, since the atomics of all wavefronts on one line are
+// served one at a time (about 11 ns each on MI355X, same address or not) and
+// appends to different classes then proceed side by side.
+constexpr int kCtr = 32;
+
 struct Ctl {
-  int32_t cnt[3][kClasses];       // sparse list sizes per class (may exceed the cap: then overflow is set)
-  int32_t overflow[3][4];         // [slot][0]: 1 when the round of this slot rebuilds its lists by compaction
-  int32_t ccnt[2][kClasses];      // list sizes produced by the compaction pass, by round parity
-  int32_t tail_cnt[2][kClasses];  // counters of the single-workgroup tail
-  int32_t pop[kClasses];          // vertices per degree class (list region sizes)
-  int32_t seed_fill[kClasses];    // first-round (static) list sizes: vertices of degree >= 2 per class
+  int32_t cnt[3][kClasses * kCtr];       // sparse list sizes per class (may exceed the cap: then overflow is set)
+  int32_t overflow[3][4];                // [slot][0]: 1 when the round of this slot rebuilds its lists by compaction
+  int32_t ccnt[2][kClasses * kCtr];      // list sizes produced by the compaction pass, by round parity
+  int32_t tail_cnt[2][kClasses * kCtr];  // counters of the single-workgroup tail
+  int32_t pop[kClasses];                 // vertices per degree class (list region sizes)
+  int32_t seed_fill[kClasses * kCtr];    // first-round (static) list sizes: vertices of degree >= 2 per class
   unsigned long long stats[16];   // run counters (ST_ROUNDS ...)
   // per round kernel (KernelId) and counter (ST_UPDATES .. ST_FULL_SCANS), spread over
   // kStatCopies addresses by workgroup so that the flushes of a launch do not all meet
@@ -154,15 +160,17 @@ struct Ctl {
   uint32_t maxscan_round;
   int32_t resid_cnt;              // class-3 vertices the wavefront pass handed to the workgroup kernel this round
   int32_t dirty_from;             // first round whose compaction may skip pieces without a dirty mark
-  // deferred same-kernel checks appended in the current round, one counter per
-  // buffer region (a workgroup appends to region blockIdx.x % kDeferRegions)
-  int32_t dcnt[128];
   // class counts of the initialisation kernels, summed into pop by k_pop_sum: a
   // workgroup adds to copy blockIdx.x % kPopCopies, one 128-byte line each, since
-  // atomics from thousands of workgroups on one address are served one at a time
+  // the atomics of thousands of workgroups on one line are served one at a time
   int32_t pop_part[kPopCopies][32];
+  // deferred same-kernel checks appended in the current round, one counter per
+  // buffer region (a workgroup appends to region blockIdx.x % kDeferRegions), at
+  // index region * kCtr
+  int32_t dcnt[kDeferRegions * kCtr];
 };
-// What the host reads of the control block (everything before the copies of the class counts).
+// What the host reads of the control block (everything before the copies of the class counts and the
+// deferred-check counters).
 constexpr size_t kCtlHostBytes = offsetof(Ctl, pop_part);
 enum Stat {
   ST_UPDATES = 0, ST_VISITS, ST_CHANGES, ST_ACTIVATIONS, ST_PRUNE_WRITES, ST_FULL_SCANS, ST_ROUNDS,

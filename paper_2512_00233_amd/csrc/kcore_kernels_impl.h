@@ -249,7 +249,7 @@ __device__ __forceinline__ void activate_changed(const Args<Off>& a, const Sink&
     const int32_t tot = __shfl(incl, kWave - 1);
     if (tot == 0) continue;
     int32_t base = 0;
-    if (lane == kWave - 1) base = atomicAdd(&s.cnt[k], tot);
+    if (lane == kWave - 1) base = atomicAdd(&s.cnt[k * kCtr], tot);
     base = __shfl(base, kWave - 1);
     int32_t pos = base + incl - mine;
 #pragma unroll
@@ -1188,7 +1188,7 @@ __device__ __forceinline__ Frontier frontier_of(const Args<Off>& a, int32_t roun
   dense = FIRST || ctl->overflow[round % 3][0] != 0;
   const int32_t* cn = FIRST ? ctl->seed_fill : (dense ? ctl->ccnt[round & 1] : ctl->cnt[round % 3]);
 #pragma unroll
-  for (int k = 0; k < kClasses; ++k) f.n[k] = cn[k];
+  for (int k = 0; k < kClasses; ++k) f.n[k] = cn[k * kCtr];
   f.list = FIRST ? a.slist : list_of(a, round);
   return f;
 }
@@ -1295,7 +1295,7 @@ __device__ __forceinline__ void tail_select(const Args<Off>& a, Frontier& f, int
       const uint64_t m = ballot(carry);
       if (m) {
         int32_t base = 0;
-        if (lane == 0) base = atomicAdd(&ncnt[k], popc(m));
+        if (lane == 0) base = atomicAdd(&ncnt[k * kCtr], popc(m));
         base = __shfl(base, 0);
         if (carry) {
           next[f.b[k] + base + lanes_below(m)] = v;
@@ -1321,8 +1321,8 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
   Ctl* ctl = a.ctl;
   const int tid = threadIdx.x;
   if (tid < kClasses) {
-    ctl->tail_cnt[0][tid] = 0;
-    ctl->tail_cnt[1][tid] = 0;
+    ctl->tail_cnt[0][tid * kCtr] = 0;
+    ctl->tail_cnt[1][tid * kCtr] = 0;
   }
   __syncthreads();
   int32_t t = 0;
@@ -1332,7 +1332,7 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
     if (t > 0) {
       f.list = list_of(a, r);
 #pragma unroll
-      for (int k = 0; k < kClasses; ++k) f.n[k] = ld_counter(&ctl->tail_cnt[t & 1][k]);
+      for (int k = 0; k < kClasses; ++k) f.n[k] = ld_counter(&ctl->tail_cnt[t & 1][k * kCtr]);
     }
     if (f.n[0] + f.n[1] + f.n[2] + f.n[3] == 0) break;
     if (t >= a.tail_cap) {
@@ -1361,14 +1361,14 @@ __device__ __forceinline__ void run_tail(const Args<Off>& a, int32_t round, cons
     else
       for (int32_t i = 0; i < f.n[3]; ++i) upd_big_lite<BLOCK, BATCH>(a, s, f.list[f.b[3] + i], r, st, red);
     __syncthreads();
-    if (t > 0 && tid < kClasses) ctl->tail_cnt[t & 1][tid] = 0;  // reused by round t+2
+    if (t > 0 && tid < kClasses) ctl->tail_cnt[t & 1][tid * kCtr] = 0;  // reused by round t+2
     __syncthreads();
   }
   // Nothing is left in the round slots: clear them (the round base then skips
   // past the stamps the tail used, so none of them is read again; a handed-back
   // frontier is restored by the base advance).
   if (tid < 12) {
-    ctl->cnt[tid / 4][tid % 4] = 0;
+    ctl->cnt[tid / 4][(tid % 4) * kCtr] = 0;
     ctl->overflow[tid / 4][tid % 4] = 0;
   }
   if (tid == 0) {
@@ -1397,7 +1397,7 @@ __global__ __launch_bounds__(256) void k_defer(Args<Off> a, int32_t slot, int32_
   const int slice = blockIdx.x / kDeferRegions;
   if (slice >= slices) return;
   const int32_t rcap = a.defer_cap / kDeferRegions;
-  const int32_t n = min(ctl->dcnt[reg], rcap);
+  const int32_t n = min(ctl->dcnt[reg * kCtr], rcap);
   if (n == 0) return;
   const int nslot = (round + 1) % 3;
   const Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
@@ -1453,7 +1453,7 @@ __global__ void k_advance(Ctl* ctl, int32_t k) {
       ctl->rbase = r;
 #pragma unroll
       for (int c = 0; c < kClasses; ++c) {
-        ctl->cnt[r % 3][c] = ctl->resume_cnt[c];
+        ctl->cnt[r % 3][c * kCtr] = ctl->resume_cnt[c];
         ctl->overflow[r % 3][c] = 0;
       }
       ctl->resume = 0;
@@ -1554,7 +1554,7 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
   Ctl* ctl = a.ctl;
   const int32_t round = ctl->rbase + slot;
   // this round's deferred checks start empty (the previous round's were consumed by its k_defer)
-  if (!SEED && blockIdx.x == 0 && threadIdx.x < kDeferRegions) ctl->dcnt[threadIdx.x] = 0;
+  if (!SEED && blockIdx.x == 0 && threadIdx.x < kDeferRegions) ctl->dcnt[threadIdx.x * kCtr] = 0;
   if (!SEED && blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->maxscan_round = 0;
     ctl->resid_cnt = 0;
@@ -1617,7 +1617,7 @@ __global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
     int32_t t = 0;
     for (int w = 0; w < NW; ++w) t += wcnt[w][threadIdx.x];
     int32_t* fill = SEED ? ctl->seed_fill : ctl->ccnt[round & 1];
-    bbase[threadIdx.x] = t ? atomicAdd(&fill[threadIdx.x], t) : 0;
+    bbase[threadIdx.x] = t ? atomicAdd(&fill[threadIdx.x * kCtr], t) : 0;
   }
   __syncthreads();
   int32_t rb[kClasses];
@@ -1658,9 +1658,9 @@ __global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t slot, int3
   bool dense = false;
   const Frontier f = frontier_of<FIRST>(a, round, dense);
   if (blockIdx.x == 0 && threadIdx.x < 4) {
-    ctl->cnt[(round + 2) % 3][threadIdx.x] = 0;
+    ctl->cnt[(round + 2) % 3][threadIdx.x * kCtr] = 0;
     ctl->overflow[(round + 2) % 3][threadIdx.x] = 0;
-    ctl->ccnt[(round + 1) & 1][threadIdx.x] = 0;  // compaction output of the next round
+    ctl->ccnt[(round + 1) & 1][threadIdx.x * kCtr] = 0;  // compaction output of the next round
   }
   LaneStats st;
   const int32_t tot = f.n[0] + f.n[1] + f.n[2] + f.n[3];
@@ -1677,7 +1677,7 @@ __global__ __launch_bounds__(BLOCK) void k_round(Args<Off> a, int32_t slot, int3
   if (FIRST) s.dirty = nullptr;  // the round after the first reads every piece
   if (!FIRST && a.defer) {
     const int reg = blockIdx.x % kDeferRegions;
-    s.dcnt = &ctl->dcnt[reg];
+    s.dcnt = &ctl->dcnt[reg * kCtr];
     s.dcap = a.defer_cap / kDeferRegions;
     s.dbase = reg * s.dcap;
   }
@@ -1709,7 +1709,7 @@ __global__ __launch_bounds__(256) void k_big_wave(Args<Off> a, int32_t slot, int
   Sink s = make_sink(a, round + 1, ctl->cnt[nslot], &ctl->overflow[nslot][0], true);
   if (a.defer) {
     const int reg = blockIdx.x % kDeferRegions;
-    s.dcnt = &ctl->dcnt[reg];
+    s.dcnt = &ctl->dcnt[reg * kCtr];
     s.dcap = a.defer_cap / kDeferRegions;
     s.dbase = reg * s.dcap;
   }
@@ -1744,7 +1744,7 @@ __global__ __launch_bounds__(kBigBlock, 4) void k_big(Args<Off> a, int32_t slot,
   if (FIRST) s.dirty = nullptr;
   if (!FIRST && a.defer) {
     const int reg = blockIdx.x % kDeferRegions;
-    s.dcnt = &ctl->dcnt[reg];
+    s.dcnt = &ctl->dcnt[reg * kCtr];
     s.dcap = a.defer_cap / kDeferRegions;
     s.dbase = reg * s.dcap;
   }
@@ -1946,8 +1946,8 @@ __global__ void k_serve_join(Ctl* ctl, int32_t p0, int32_t p1, int32_t p2, int32
   const int32_t r = ctl->rbase;
   if (k < kClasses) {
     ctl->pop[k] = k == 0 ? p0 : (k == 1 ? p1 : (k == 2 ? p2 : p3));
-    ctl->ccnt[r & 1][k] = 0;
-    ctl->cnt[(r + 1) % 3][k] = 0;
+    ctl->ccnt[r & 1][k * kCtr] = 0;
+    ctl->cnt[(r + 1) % 3][k * kCtr] = 0;
     ctl->overflow[(r + 1) % 3][k] = 0;
   }
   if (k == 0) {

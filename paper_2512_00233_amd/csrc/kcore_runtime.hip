@@ -567,7 +567,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
     std::fprintf(stderr, "[kcore-trace] %s round=%d front=%d/%d/%d/%d dense=%d | big upd=%llu vis=%llu chg=%llu "
                  "act=%llu full=%llu maxscan=%u big_ms=%.3f | small upd=%llu vis=%llu chg=%llu act=%llu full=%llu | "
                  "tail=%llu ms=%.3f\n",
-                 what, r - r0, h.cnt[r % 3][0], h.cnt[r % 3][1], h.cnt[r % 3][2], h.cnt[r % 3][3],
+                 what, r - r0, h.cnt[r % 3][0], h.cnt[r % 3][kCtr], h.cnt[r % 3][2 * kCtr], h.cnt[r % 3][3 * kCtr],
                  h.overflow[r % 3][0], d[0][ST_UPDATES], d[0][ST_VISITS], d[0][ST_CHANGES], d[0][ST_ACTIVATIONS],
                  d[0][ST_FULL_SCANS], h.maxscan_round, big_ms, d[1][ST_UPDATES], d[1][ST_VISITS], d[1][ST_CHANGES],
                  d[1][ST_ACTIVATIONS], d[1][ST_FULL_SCANS], h.stats[ST_TAIL_ROUNDS], ms);
@@ -623,7 +623,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
       }
     }
     const int32_t* c = h.cnt[r % 3];
-    if (h.overflow[r % 3][0] == 0 && c[0] == 0 && c[1] == 0 && c[2] == 0 && c[3] == 0) break;
+    if (h.overflow[r % 3][0] == 0 && c[0] == 0 && c[kCtr] == 0 && c[2 * kCtr] == 0 && c[3 * kCtr] == 0) break;
     // Every round but the last lowers an estimate (a round without a change
     // activates nobody), and the estimates fall by at most the sum of the
     // degrees: more rounds than that mean a fault, not a long run.
