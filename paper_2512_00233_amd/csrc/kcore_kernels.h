@@ -142,9 +142,10 @@ struct Ctl {
   int32_t pop[kClasses];                 // vertices per degree class (list region sizes)
   int32_t seed_fill[kClasses * kCtr];    // first-round (static) list sizes: vertices of degree >= 2 per class
   unsigned long long stats[16];   // run counters (ST_ROUNDS ...)
-  // per round kernel (KernelId) and counter (ST_UPDATES .. ST_FULL_SCANS), spread over
-  // kStatCopies addresses by workgroup so that the flushes of a launch do not all meet
-  unsigned long long kstats[5][6][16];
+  // per round kernel (KernelId) and counter (ST_UPDATES .. ST_FULL_SCANS), in kStatCopies
+  // copies by workgroup, copy-major: one counter's copies lie 240 bytes apart, on different
+  // lines, so that the flushes of a launch do not all meet on one line
+  unsigned long long kstats[32][5][6];
   int32_t rbase;                  // round number of slot 0 of the next chunk of round launches
   int32_t tail_pending;           // rounds run by a tail since the last base advance (stamps up to rbase + this)
   int32_t nhi;                    // served graphs: vertex-id bound of the live slots (compaction range)
@@ -177,7 +178,8 @@ enum Stat {
   ST_TAIL_ROUNDS, ST_DENSE_ROUNDS
 };
 constexpr int kLaneStats = 6;  // stats accumulated per lane (ST_UPDATES .. ST_FULL_SCANS)
-constexpr int kStatCopies = 16;
+constexpr int kStatCopies = 32;
+static_assert(sizeof(Ctl::kstats) / sizeof(Ctl::kstats[0]) == kStatCopies, "statistics copies");
 // Round kernels whose work is counted separately (the first round's two, the later rounds' two).
 // (and the deferred checks, whose activations are counted too)
 enum KernelId { KI_BIG_FIRST = 0, KI_ROUND_FIRST, KI_BIG, KI_ROUND, KI_DEFER, KI_COUNT };

@@ -1167,7 +1167,7 @@ __device__ __forceinline__ void flush_stats(Ctl* ctl, int kid, const LaneStats& 
   if (threadIdx.x < kLaneStats) {
     unsigned long long t = 0;
     for (int w = 0; w < NW; ++w) t += red64[threadIdx.x * NW + w];
-    if (t) atomicAdd(&ctl->kstats[kid][threadIdx.x][blockIdx.x % kStatCopies], t);
+    if (t) atomicAdd(&ctl->kstats[blockIdx.x % kStatCopies][kid][threadIdx.x], t);
   }
 }
 

@@ -442,7 +442,7 @@ static void launch_round_timed(const Args<Off>& a, const Tuning& tu, int cgrid, 
 // A kernel's counter, summed over its copies.
 static unsigned long long kstat(const Ctl& h, int kid, int q) {
   unsigned long long t = 0;
-  for (int c = 0; c < kStatCopies; ++c) t += h.kstats[kid][q][c];
+  for (int c = 0; c < kStatCopies; ++c) t += h.kstats[c][kid][q];
   return t;
 }
 
