@@ -92,6 +92,10 @@ constexpr int kKary = 3;
 constexpr int kHistBins = 4096;     // LDS histogram bins of the one-pass search (16 KB)
 constexpr int kStash = 8192;        // LDS copies (16-bit) of the values read by the one-pass search (16 KB)
 constexpr int kCompactPerLane = 16; // vertices per lane read at once by the compaction kernel
+// Threads of a compaction workgroup: each workgroup reserves its list space with
+// one atomic per class, and atomics on one line are served one at a time, so
+// fewer, larger workgroups (the same wavefronts in all) wait less.
+constexpr int kCompactBlock = 1024;
 constexpr int kCompactPiece = 64 * kCompactPerLane;  // vertices a wavefront reads at once (a dirty-mark piece)
 constexpr int kCompactPieceShift = 10;
 static_assert(kCompactPiece == 1 << kCompactPieceShift, "piece size");

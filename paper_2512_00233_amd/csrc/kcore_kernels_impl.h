@@ -1547,8 +1547,8 @@ __global__ __launch_bounds__(256) void k_init(Args<Off> a, int32_t r0, int32_t t
 // once: a counting pass, one atomic per workgroup and class, then a writing
 // pass over the same range.
 template <bool SEED, typename Off>
-__global__ __launch_bounds__(256) void k_compact(Args<Off> a, int32_t slot) {
-  constexpr int BLOCK = 256, NW = BLOCK / kWave, P = kCompactPerLane, PIECE = kWave * P;
+__global__ __launch_bounds__(kCompactBlock) void k_compact(Args<Off> a, int32_t slot) {
+  constexpr int BLOCK = kCompactBlock, NW = BLOCK / kWave, P = kCompactPerLane, PIECE = kWave * P;
   __shared__ int32_t wcnt[NW][kClasses];
   __shared__ int32_t bbase[kClasses];
   Ctl* ctl = a.ctl;

@@ -344,8 +344,8 @@ constexpr int kBlock = 256;
 // vertices per lane each, at most 16 per compute unit (measured on the 2048-graph
 // batch's compaction: 61 ms with two per unit, 37 ms with eight, 33 ms with 16).
 static int compact_grid(int64_t n, int num_cus) {
-  const int64_t per_block = (int64_t)kBlock * kCompactPerLane * 4;
-  return (int)std::max<int64_t>(1, std::min<int64_t>((n + per_block - 1) / per_block, 16 * (int64_t)num_cus));
+  const int64_t per_block = (int64_t)kCompactBlock * kCompactPerLane * 4;
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + per_block - 1) / per_block, 4 * (int64_t)num_cus));
 }
 
 // The two update kernels of a round (slot relative to the round base), in
@@ -378,7 +378,7 @@ static void launch_updates(const Args<Off>& a, const Tuning& tu, int32_t slot, i
 // The compaction of a round (a no-op unless its lists overflowed).
 template <typename Off>
 static void launch_compact(const Args<Off>& a, int cgrid, int32_t slot, hipStream_t st) {
-  hipLaunchKernelGGL((k_compact<false, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, slot);
+  hipLaunchKernelGGL((k_compact<false, Off>), dim3(cgrid), dim3(kCompactBlock), 0, st, a, slot);
 }
 
 // Launch one chunk of K rounds (slots 0..K-1 relative to ctl->rbase) and
@@ -531,7 +531,7 @@ static kcore_status run_rounds(Workspace* ws, int64_t n, int64_t nnz, const Off*
   } else {
     hipLaunchKernelGGL(k_init<Off>, dim3(init_grid), dim3(kBlock), 0, st, a, r0, tu.t0, tu.t1, tu.t2);
     hipLaunchKernelGGL(k_pop_sum, dim3(1), dim3(64), 0, st, ws->ctl);
-    hipLaunchKernelGGL((k_compact<true, Off>), dim3(cgrid), dim3(kBlock), 0, st, a, 0);
+    hipLaunchKernelGGL((k_compact<true, Off>), dim3(cgrid), dim3(kCompactBlock), 0, st, a, 0);
     launch_updates<true, BATCH, Off>(a, tu, 0, collect, st, timing ? ev + 1 : nullptr);
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, ws->ctl, 1);
   }
@@ -1428,7 +1428,7 @@ kcore_status serve_step(ServeArena* A, int32_t rounds, int32_t nslots, int32_t* 
   const int cgrid = compact_grid(A->nv, A->num_cus);
   auto enqueue = [&]() {
     for (int i = 0; i < rounds; ++i) {
-      hipLaunchKernelGGL((k_compact<false, int64_t>), dim3(cgrid), dim3(kBlock), 0, st, a, i);
+      hipLaunchKernelGGL((k_compact<false, int64_t>), dim3(cgrid), dim3(kCompactBlock), 0, st, a, i);
       launch_updates<false, true, int64_t>(a, tu, i, 0, st, nullptr);
     }
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, a.ctl, rounds);
