@@ -2107,11 +2107,44 @@ __global__ __launch_bounds__(256) void k_upd_bfs_start(const int32_t* ins, int64
 // from a state of window top c (threshold rule: c unused): the new states are
 // appended to out_q.  Loads, gathers and flag updates of the slice are issued
 // together, then one atomic reserves the wavefront's places in the queue.
+// A wavefront's staging buffer in LDS for the states a search level finds: they
+// go to the output queue up to kBfsBuf at a time, with one atomic on the queue's
+// counter per flush, since the appends of every wavefront of a level meet on
+// that counter's line (served one at a time, about 11 ns each).
+constexpr int kBfsBuf = 1024;
+struct StateBuf {
+  int32_t* buf;  // kBfsBuf entries of LDS
+  int32_t held;  // entries held (the same in every lane)
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The held states to the queue (the whole wavefront calls this).
+__device__ __forceinline__ void bfs_flush(StateBuf& b, const UpdSearch& q, int32_t* out_q, int32_t* out_cnt) {
+  if (b.held == 0) return;
+  wave_lds_sync();
+  int32_t base = 0;
+  if (lane_id() == 0) base = atomicAdd(out_cnt, b.held);
+  base = __shfl(base, 0);
+  for (int32_t j = lane_id(); j < b.held; j += kWave) {
+    const int64_t pos = (int64_t)base + j;
+    if (pos < q.cap) out_q[pos] = b.buf[j];
+  }
+  wave_lds_sync();
+  b.held = 0;
+}
+
 // With Src (the sources of the heavy-vertex search) every neighbour outside Z is
-// taken, at window offset 0, whatever its old coreness.
+// taken, at window offset 0, whatever its old coreness.  The new states go to
+// the wavefront's staging buffer sb.
 template <bool Src = false, typename Off>
 __device__ __forceinline__ void bfs_slice(const int32_t* col, const int32_t* prev, const UpdSearch& q, int32_t c,
-                                          Off j0, Off e, int32_t* out_q, int32_t* out_cnt) {
+                                          Off j0, Off e, int32_t* out_q, int32_t* out_cnt, StateBuf& sb) {
+  static_assert(kBfsSlice <= kBfsBuf, "a slice's states fit an empty buffer");
   constexpr int K = kBfsSlice / kWave;
   const int lane = lane_id();
   const int32_t lo = q.D ? c + 1 - q.D : q.T, hi = q.D ? c : INT32_MAX;
@@ -2146,15 +2179,14 @@ __device__ __forceinline__ void bfs_slice(const int32_t* col, const int32_t* pre
     total += popc(m[k]);
   }
   if (total == 0) return;
-  int32_t base = 0;
-  if (lane == 0) base = atomicAdd(out_cnt, total);
-  base = __shfl(base, 0);
+  if (sb.held + total > kBfsBuf) bfs_flush(sb, q, out_q, out_cnt);
+  int32_t at = sb.held;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int64_t pos = (int64_t)base + lanes_below(m[k]);
-    if (add[k] && pos < q.cap) out_q[pos] = (int32_t)((uint32_t)w[k] | (uint32_t)off[k] << 30);
-    base += popc(m[k]);
+    if (add[k]) sb.buf[at + lanes_below(m[k])] = (int32_t)((uint32_t)w[k] | (uint32_t)off[k] << 30);
+    at += popc(m[k]);
   }
+  sb.held = at;
 }
 
 // One level of the search: one wavefront per queued state.  A row longer than
@@ -2178,6 +2210,8 @@ __global__ __launch_bounds__(256) void k_upd_bfs_level(const Off* row_ptr, const
     *stale_long_cnt = 0;
     *reached += (unsigned long long)*in_cnt;
   }
+  __shared__ int32_t stage[(256 / kWave) * kBfsBuf];
+  StateBuf sb{stage + (threadIdx.x / kWave) * kBfsBuf, 0};
   const int64_t nq = min((int64_t)*in_cnt, q.cap);
   const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < nq; i += nw) {
@@ -2195,8 +2229,9 @@ __global__ __launch_bounds__(256) void k_upd_bfs_level(const Off* row_ptr, const
       continue;
     }
     const int32_t c = prev[u] + state_offset(q, st);
-    for (Off j0 = b; j0 < e; j0 += kBfsSlice) bfs_slice(col, prev, q, c, j0, e, out_q, out_cnt);
+    for (Off j0 = b; j0 < e; j0 += kBfsSlice) bfs_slice(col, prev, q, c, j0, e, out_q, out_cnt, sb);
   }
+  bfs_flush(sb, q, out_q, out_cnt);
 }
 
 // Slices of the rows registered in long_q as (state, first slice number), the
@@ -2242,9 +2277,12 @@ __global__ __launch_bounds__(256) void k_upd_bfs_long(const Off* row_ptr, const 
                                                       UpdSearch q, const int32_t* long_q,
                                                       const unsigned long long* long_cnt, int32_t* out_q,
                                                       int32_t* out_cnt) {
+  __shared__ int32_t stage[(256 / kWave) * kBfsBuf];
+  StateBuf sb{stage + (threadIdx.x / kWave) * kBfsBuf, 0};
   for_long_slices(row_ptr, q, long_q, *long_cnt, [&](uint32_t st, Off j0, Off e) {
-    bfs_slice(col, prev, q, prev[state_vertex(q, st)] + state_offset(q, st), j0, e, out_q, out_cnt);
+    bfs_slice(col, prev, q, prev[state_vertex(q, st)] + state_offset(q, st), j0, e, out_q, out_cnt, sb);
   });
+  bfs_flush(sb, q, out_q, out_cnt);
 }
 
 // Levels of the search inside one workgroup of kBfsSmallBlock threads, from
@@ -2436,9 +2474,12 @@ __global__ __launch_bounds__(256) void k_upd_zsrc(const Off* row_ptr, const int3
     atomicOr(&q.flag[z], 2);
   }
   if (!sources) return;
+  __shared__ int32_t stage[(256 / kWave) * kBfsBuf];
+  StateBuf sb{stage + (threadIdx.x / kWave) * kBfsBuf, 0};
   for_long_slices(row_ptr, q, long_q, lc, [&](uint32_t, Off j0, Off e) {
-    bfs_slice<true>(col, prev, q, 0, j0, e, queue, qcnt);
+    bfs_slice<true>(col, prev, q, 0, j0, e, queue, qcnt, sb);
   });
+  bfs_flush(sb, q, queue, qcnt);
 }
 
 // Start of an update run: estimates from the bounds above, classes and class
